@@ -1,0 +1,132 @@
+/* oracle_md.h -- FP64 CPU reference for the per-timestep path of united-atom
+ * polyethylene molecular dynamics (Xu et al., "Molecular Dynamics Simulation of
+ * Macromolecules Using Graphics Processing Unit").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  The GPU library shares no
+ * code, header, table or helper with it.
+ *
+ * It computes, plainly and slowly, in double precision:
+ *   - the wrap of positions into the periodic box and the cell index of each atom
+ *     (Section 3.1: grid of cells with edge at least the cutoff);
+ *   - the counting sort of atoms into cells (Section 3.1, the binning step);
+ *   - the truncated Lennard-Jones force, energy and virial (Eq. 2; Section 3.2),
+ *     both by brute force over all pairs and by the paper's grid search over the
+ *     neighbouring cells, with only 1-2 and 1-3 chain neighbours excluded
+ *     (Section 3.1, Dreiding II);
+ *   - bond, angle and dihedral forces and energies (Eqs. 4-6; Section 3.3);
+ *   - one velocity-Verlet step with optional Berendsen scaling (Section 3.4
+ *     integrates with leap-frog, whose positions are the same).
+ *
+ * Units: Angstrom, fs, g/mol, kcal/mol, K.  Every array is caller-owned host
+ * memory; coordinates are structure-of-arrays.  Functions return 0 on success and
+ * a negative value on bad arguments.  Nothing here allocates memory that outlives
+ * a call.
+ */
+#ifndef ORACLE_MD_H
+#define ORACLE_MD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  double mass[2];      /* g/mol; type 0 = CH2 (C_32), 1 = CH3 (C_33) */
+  double sigma[2];     /* A */
+  double epsilon[2];   /* kcal/mol */
+  double kb, b0;       /* Eq. (4): kcal/mol/A^2, A */
+  double ka, theta0_deg;  /* Eq. (5): kcal/mol/rad^2, degrees */
+  double kphi, phis_deg;  /* Eq. (6): kcal/mol, degrees */
+  int32_t n_dih;          /* Eq. (6) periodicity */
+  double rc;              /* cutoff, A; pairs with r < rc interact */
+  int32_t excl_depth;     /* pairs closer than this many bonds along a chain are excluded */
+} ora_ff;
+
+/* Energies and virial of one configuration. */
+typedef struct {
+  double e_lj, e_lj_shifted, e_bond, e_angle, e_dih, virial_lj, virial_bonded;
+} ora_energy;
+
+int ora_set_threads(int n);   /* OpenMP threads for the per-atom loops; returns threads in use */
+
+/* Wrap each coordinate into [0, L_d) in place: if outside, s = floor(x * invL),
+   x = fma(-s, L, x), then one correction by L each way.  invL = 1/L. */
+int ora_wrap(int64_t n, double* x, double* y, double* z, const double L[3]);
+
+/* Cell index per atom: k_d = clamp(floor(x_d * (M_d / L_d)), 0, M_d - 1),
+   cell = k_x + M_x * (k_y + M_y * k_z). */
+int ora_cell_index(int64_t n, const double* x, const double* y, const double* z,
+                   const double L[3], const int32_t M[3], int32_t* cell);
+
+/* Counting sort: cnt[c] atoms per cell, cell_start = exclusive prefix sum of cnt
+   (n_cells + 1 entries), cell_atoms lists atoms of each cell in ascending index. */
+int ora_bin(int64_t n, const int32_t* cell, int64_t n_cells, int32_t* cnt, int32_t* cell_start,
+            int32_t* cell_atoms);
+
+/* Lennard-Jones by brute force over all unordered pairs (minimum image).
+   Forces are written (not accumulated). */
+int ora_lj_brute(const ora_ff* ff, int64_t n, int32_t chain_len, const double* x, const double* y,
+                 const double* z, const uint8_t* type, const double L[3], double* fx, double* fy,
+                 double* fz, ora_energy* e);
+
+/* Lennard-Jones by the grid search: each atom visits the (2R+1)^3 cells around its
+   own (R = stencil radius, M_d >= 2R+1, L_d / M_d >= rc / R), every pair from both
+   sides.  If `subset` is non-null only atoms subset[0..n_subset) get forces (others
+   are left untouched) and e may be null. */
+int ora_lj_cells(const ora_ff* ff, int64_t n, int32_t chain_len, const double* x, const double* y,
+                 const double* z, const uint8_t* type, const double L[3], const int32_t M[3],
+                 int32_t R, const int64_t* subset, int64_t n_subset, double* fx, double* fy,
+                 double* fz, ora_energy* e);
+
+/* Bond, angle and dihedral terms of linear chains of chain_len atoms (atom c*chain_len+p
+   is site p of chain c).  Forces are ADDED to fx, fy, fz. */
+int ora_bonded(const ora_ff* ff, int64_t n, int32_t chain_len, const double* x, const double* y,
+               const double* z, const double L[3], double* fx, double* fy, double* fz,
+               ora_energy* e);
+
+/* The bonded terms of one chain as the oracle enumerates them: k = 2 (bonds),
+   3 (angles), 4 (dihedrals); writes up to max_terms tuples of k 0-based site indices
+   to out and returns the number of terms. */
+int ora_chain_terms(int32_t chain_len, int32_t k, int32_t* out, int32_t max_terms);
+
+/* Single-term helpers on explicit coordinates (no periodicity); forces written to f[3*k]. */
+double ora_bond_term(const ora_ff* ff, const double* xi, const double* xj, double* f);
+double ora_angle_term(const ora_ff* ff, const double* xi, const double* xj, const double* xk,
+                      double* f, double* theta_out);
+double ora_dihedral_term(const ora_ff* ff, const double* xi, const double* xj, const double* xk,
+                         const double* xl, double* f, double* phi_out);
+
+/* Total force (LJ by grid search with stencil radius R, plus bonded). */
+int ora_forces(const ora_ff* ff, int64_t n, int32_t chain_len, const double* x, const double* y,
+               const double* z, const uint8_t* type, const double L[3], const int32_t M[3],
+               int32_t R, double* fx, double* fy, double* fz, ora_energy* e);
+
+/* Compensated (Neumaier) sum of v[0..n) in index order. */
+double ora_sum(int64_t n, const double* v);
+
+/* Kinetic energy (kcal/mol) and temperature (K, 3N-3 degrees of freedom). */
+int ora_kinetic(const ora_ff* ff, int64_t n, const double* vx, const double* vy, const double* vz,
+                const uint8_t* type, double* ke, double* temperature);
+
+typedef struct {
+  double dt;     /* fs */
+  double tau;    /* fs, Berendsen coupling time */
+  double T0;     /* K; <= 0 disables the thermostat (NVE) */
+} ora_integ;
+
+/* n_steps of velocity Verlet on one box.  On entry f holds the total force at x;
+   on exit x, v and f are advanced.  Per step: v += dt/2 a; x += dt v; wrap;
+   f = F(x); v += dt/2 a; KE, T; if T0 > 0, v *= lambda with
+   lambda = sqrt(1 + dt/tau (T0/T - 1)).  e_out / ke_out / t_out (may be null) get
+   the energies of the last step (kinetic energy and temperature before scaling). */
+int ora_run(const ora_ff* ff, const ora_integ* in, int64_t n, int32_t chain_len, double* x,
+            double* y, double* z, double* vx, double* vy, double* vz, double* fx, double* fy,
+            double* fz, const uint8_t* type, const double L[3], const int32_t M[3], int32_t R,
+            int32_t n_steps, ora_energy* e_out, double* ke_out, double* t_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
