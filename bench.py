@@ -1,0 +1,208 @@
+"""Benchmark: atom-steps/s of the all-GPU polyethylene MD step on one MI355X.
+
+Default workload: 1,000 chains x 300 united atoms (300,000 atoms), 0.80 g/cm^3, Maxwell
+velocities at 500 K, Berendsen quench towards 300 K, dt = 1 fs, bins rebuilt every step,
+mixed precision (FP32 forces, FP64 state), hipGraph-replayed steps.  Beside it: the plain
+FP64 GPU form on the same input (the paper's grid of cells of edge >= cutoff, no graph),
+the force error of the mixed form against the FP64 oracle, per-phase kernel times, the
+roofline position of the Lennard-Jones kernel, and the FP64 CPU oracle timed on a bounded
+sample of the same workload.
+
+Prints ONE JSON line.  Inputs are synthetic (seeded melts); see pe_melt.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "atom-steps/s (and ns/day) mixed/batched vs plain FP64 GPU at <=1e-5 force err"
+PEAK_FP32_TFLOPS = 157.3      # MI355X FP32 vector (vendor figure)
+LJ_FLOP_PER_CANDIDATE = 8     # 3 sub, 1 mul + 2 fma (=4) for r^2, 1 compare
+LJ_FLOP_PER_PAIR = 13         # rcp, r^-6 (2 mul), force factor (fma + 2 mul), 3 fma accumulations
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def candidate_and_pair_counts(pos, box, start, M, R, rc, n_chains, chain_len):
+    """Candidates the stencil walk tests (sum over atoms of the atoms in the (2R+1)^3 cells
+    around its cell) and in-cutoff ordered pairs (excluding self and 1-2/1-3 chain pairs)."""
+    import numpy as np
+    from scipy.spatial import cKDTree
+    cnt = np.diff(start).reshape(M[2], M[1], M[0]).astype(np.int64)
+    neigh = np.zeros_like(cnt)
+    for oz in range(-R, R + 1):
+        for oy in range(-R, R + 1):
+            for ox in range(-R, R + 1):
+                neigh += np.roll(cnt, shift=(oz, oy, ox), axis=(0, 1, 2))
+    candidates = int((cnt * neigh).sum())
+    p = np.mod(pos.T, box)
+    p = np.minimum(p, np.nextafter(box, 0))
+    tree = cKDTree(p, boxsize=box)
+    n_le = int(tree.count_neighbors(tree, rc * (1 - 1e-12)))
+    excluded = n_chains * 2 * ((chain_len - 1) + (chain_len - 2))
+    pairs = n_le - pos.shape[1] - excluded
+    return candidates, pairs
+
+
+def cpu_baseline(ff, melt, budget_s=12.0, max_steps=20):
+    import numpy as np
+    import oracle as O
+    threads = O.set_threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+    f0, _ = O.forces(ff, melt.pos, melt.types, melt.box, melt.chain_len)
+    p, v, f = melt.pos, melt.vel, f0
+    steps = 0
+    t0 = time.perf_counter()
+    while steps < max_steps:
+        p, v, f, _ = O.run(ff, p, v, f, melt.types, melt.box, melt.chain_len, 1, T0=300.0)
+        steps += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": melt.n_atoms * steps / dt, "unit": "atom-steps/s", "cores": threads, "kind": "oracle",
+            "sample": "%d step(s) of the same %d-atom melt (FP64 C oracle, OpenMP over atoms), %.1f s"
+                      % (steps, melt.n_atoms, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--fp64-steps", type=int, default=1000)
+    ap.add_argument("--cell-div", type=int, default=0, help="0 = autotune")
+    ap.add_argument("--lj-kernel", type=int, default=0, help="0 = autotune")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only (one process, no collectives); --gpus %d is not supported"
+              % args.gpus, flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1001_3764_amd.md import MDSystem
+    from pe_melt import WORKLOADS, make_melt, polyethylene_forcefield
+
+    wl = WORKLOADS["melt300k_mixed"]
+    ff = polyethylene_forcefield()
+    t = time.perf_counter()
+    melt = make_melt(wl.n_chains[0], density=wl.density, T=wl.T_init[0], seed_melt=wl.seeds[0][0],
+                     seed_vel=wl.seeds[0][1])
+    log("melt: %d atoms, L=%.3f A (%.1fs)" % (melt.n_atoms, melt.box[0], time.perf_counter() - t))
+    N = melt.n_atoms
+    dev = torch.device("cuda:0")
+
+    # ---- mixed precision, graph-replayed: the headline ----
+    s = MDSystem(ff, [melt.n_chains], melt.box[None, :], [wl.T0[0]], melt.pos, melt.vel, melt.types,
+                 chain_len=wl.chain_len, dt=wl.dt_fs, tau=wl.tau_fs, precision="mixed",
+                 cell_div=args.cell_div, lj_kernel=args.lj_kernel, use_graph=not args.no_graph, device=dev)
+    R, kern = s.tuning()
+    log("mixed: cell_div R=%d, lj kernel %d" % (R, kern))
+    f_mixed = s.forces()
+    start0, _ = s.bins()
+    M, _, _ = s.grid(0)
+    s.step(args.warmup)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    s.step(args.steps)
+    torch.cuda.synchronize(dev)
+    t1 = time.perf_counter()
+    e_end = s.energies()[0]
+    wall = t1 - t0
+    value = N * args.steps / wall
+    ms_per_step = 1e3 * wall / args.steps
+    log("mixed: %.3f ms/step, %.3e atom-steps/s, T=%.1f K" % (ms_per_step, value, e_end["temperature"]))
+
+    # per-phase kernel durations, HIP events on the library's stream
+    n_prof = min(args.steps, 500)
+    phases = s.step_timed(n_prof)
+    phase_avg = {k: v / n_prof for k, v in phases.items()}
+    start_prof, _ = s.bins()
+    pos_prof, _ = s.state()
+    s.close()
+
+    cand, pairs = candidate_and_pair_counts(pos_prof, melt.box, start_prof, M, R, ff["rc"], melt.n_chains,
+                                            melt.chain_len)
+    lj_ms = phase_avg["lj"]
+    flop = LJ_FLOP_PER_CANDIDATE * cand + LJ_FLOP_PER_PAIR * pairs
+    achieved = flop / (lj_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "kernel": "k_lj (Lennard-Jones, mixed)", "avg_launch_ms": round(lj_ms, 5),
+                "candidates_per_launch": cand, "pairs_per_launch": pairs, "flop_per_launch": flop}
+
+    # ---- force error of the mixed form against the FP64 oracle at the initial state ----
+    force_err = None
+    try:
+        import oracle as O
+        O.set_threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+        fo, _ = O.forces(ff, melt.pos, melt.types, melt.box, melt.chain_len)
+        frms = np.sqrt(np.mean(np.sum(fo ** 2, axis=0)))
+        force_err = float(np.max(np.sqrt(np.sum((f_mixed - fo) ** 2, axis=0))) / frms)
+        log("mixed force error vs oracle: %.3e" % force_err)
+    except Exception as exc:   # the metric line is still printed
+        log("force error check failed: %r" % (exc,))
+
+    # ---- plain FP64 GPU form (the paper's grid, no graph) ----
+    plain = None
+    if not args.no_fp64:
+        s64 = MDSystem(ff, [melt.n_chains], melt.box[None, :], [wl.T0[0]], melt.pos, melt.vel, melt.types,
+                       chain_len=wl.chain_len, dt=wl.dt_fs, tau=wl.tau_fs, precision="fp64", cell_div=1,
+                       lj_kernel=1, use_graph=False, device=dev)
+        s64.step(min(args.warmup, 20))
+        torch.cuda.synchronize(dev)
+        a = time.perf_counter()
+        s64.step(args.fp64_steps)
+        torch.cuda.synchronize(dev)
+        b = time.perf_counter()
+        s64.close()
+        v64 = N * args.fp64_steps / (b - a)
+        plain = {"value": v64, "unit": "atom-steps/s", "steps": args.fp64_steps,
+                 "ms_per_step": 1e3 * (b - a) / args.fp64_steps}
+        log("fp64: %.3f ms/step, %.3e atom-steps/s" % (plain["ms_per_step"], v64))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        try:
+            cpu = cpu_baseline(ff, melt)
+            log("cpu oracle: %.3e atom-steps/s on %d threads" % (cpu["value"], cpu["cores"]))
+        except Exception as exc:
+            log("cpu baseline failed: %r" % (exc,))
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "atom-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": wl.name, "atoms": N, "chains": melt.n_chains, "chain_len": melt.chain_len,
+                   "density_g_cm3": wl.density, "box_A": round(float(melt.box[0]), 4),
+                   "T_init_K": wl.T_init[0], "T0_K": wl.T0[0], "thermostat": "berendsen",
+                   "tau_fs": wl.tau_fs, "dt_fs": wl.dt_fs, "precision": "mixed (FP32 force, FP64 state)",
+                   "cell_div": R, "cells_per_dim": [int(x) for x in M], "lj_kernel": kern,
+                   "graph": not args.no_graph, "bins_rebuilt_every_step": True},
+        "ns_per_day": (1e3 / ms_per_step) * wl.dt_fs * 86400 * 1e-6,
+        "force_err_vs_fp64_oracle": force_err,
+        "plain_fp64_gpu": plain,
+        "speedup_vs_plain_fp64": (value / plain["value"]) if plain else None,
+        "phases_ms_avg": {k: round(v, 5) for k, v in phase_avg.items()},
+        "final_temperature_K": e_end["temperature"],
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,197 @@
+/* md.h -- C ABI of the MI355X (gfx950) library for the per-timestep hot path of
+ * united-atom polyethylene molecular dynamics, after Xu, Ren, Ge, Yu, Yang, Li,
+ * "Molecular Dynamics Simulation of Macromolecules Using Graphics Processing Unit".
+ *
+ * One time step, all on the GPU (Section 3, Figure 1):
+ *   - bin rebuild (Section 3.1): wrap positions into the periodic box, cell index per
+ *     atom, count per cell, exclusive scan, stable scatter into cell lists, and a
+ *     sorted coordinate payload for the force kernel;
+ *   - non-bonded force (Section 3.2, Eq. 2): truncated Lennard-Jones over the cells
+ *     around each atom's cell, excluding only 1-2 and 1-3 chain neighbours;
+ *   - bonded forces (Section 3.3, Eqs. 3-6): bond, angle and dihedral terms of the
+ *     linear chains;
+ *   - update (Section 3.4): velocity Verlet (the same positions as the paper's
+ *     leap-frog) with optional Berendsen velocity scaling, and per-box kinetic
+ *     energy, potential energies and virial summed in compensated double precision.
+ *
+ * Units: Angstrom, fs, g/mol, kcal/mol, K.
+ *
+ * Memory.  The library allocates no device memory.  Positions, velocities, types
+ * and one workspace are caller-owned device buffers (for instance torch tensors);
+ * they must outlive the context, which keeps non-owning pointers.  Coordinates are
+ * structure-of-arrays: pos[0..N) = x, pos[N..2N) = y, pos[2N..3N) = z, FP64.
+ * Several independent periodic boxes may be simulated at once ("batched"): box b
+ * owns the contiguous atoms [atom_offset(b), atom_offset(b) + n_chains[b] * chain_len),
+ * and its chains are contiguous runs of chain_len atoms; atom c*chain_len + p is
+ * site p of chain c (0-based; the paper's indices are 1-based).
+ *
+ * Streams.  Every call enqueues work on the HIP stream given at init and returns
+ * without waiting, except md_energies, md_tuning and md_destroy, which synchronise
+ * that stream.  Calls on one context must not overlap from several host threads.
+ *
+ * Errors.  Every function returns md_status and never throws.  Argument errors are
+ * detected on the host before anything is enqueued.  Errors found on the device
+ * (non-finite positions or forces) set a sticky device word that the next
+ * md_energies reports; the context then refuses md_step until re-initialised.
+ */
+#ifndef MD_H
+#define MD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MD_OK = 0,
+  MD_ERR_ARG = -1,            /* null pointer, bad size or inconsistent configuration */
+  MD_ERR_BOX_TOO_SMALL = -2,  /* a box has fewer than 2R+1 cells along a dimension */
+  MD_ERR_NONFINITE = -3,      /* a coordinate or force became NaN or infinite (device) */
+  MD_ERR_WORKSPACE = -4,      /* workspace smaller than md_workspace_bytes, or misaligned */
+  MD_ERR_HIP = -6,            /* a HIP runtime call failed; md_last_error has the text */
+  MD_ERR_STATE = -7           /* the context is in an error state; re-initialise it */
+} md_status;
+
+typedef enum {
+  MD_PREC_FP64 = 0,   /* every force, energy and state update in double precision */
+  MD_PREC_MIXED = 1   /* pair and bonded forces in FP32 with FP32 per-atom accumulation;
+                         positions, velocities and the update in FP64; energy and virial
+                         sums in compensated FP64 */
+} md_precision;
+
+typedef enum {
+  MD_LJ_AUTO = 0,       /* chosen by the autotuner at init */
+  MD_LJ_ATOM = 1,       /* one lane per home atom walking the neighbouring cells */
+  MD_LJ_CELLTILE = 2    /* one wavefront per home cell: home atoms wave-uniform, candidate
+                           atoms across the lanes */
+} md_lj_kernel;
+
+/* Force field (Table I, Eqs. 2-6).  Types: 0 = CH2 (C_32), 1 = CH3 (C_33).  LJ pair
+   parameters follow Lorentz-Berthelot mixing. */
+typedef struct {
+  double mass[2];         /* g/mol */
+  double sigma[2];        /* A */
+  double epsilon[2];      /* kcal/mol */
+  double kb, b0;          /* Eq. (4): E = kb/2 (r - b0)^2; kcal/mol/A^2, A */
+  double ka, theta0_deg;  /* Eq. (5): E = ka/2 (theta - theta0)^2; kcal/mol/rad^2, deg */
+  double kphi, phis_deg;  /* Eq. (6): E = kphi (1 + cos(n phi - phis)); kcal/mol, deg; */
+  int32_t n_dih;          /*   phi is IUPAC (trans = 180 deg), n >= 1 */
+  double rc;              /* cutoff, A: a pair interacts iff r < rc */
+  int32_t excl_depth;     /* pairs at most this many bonds apart on a chain are excluded
+                             (2 = the 1-2 and 1-3 exclusions of Dreiding II, Section 3.1) */
+} md_forcefield;
+
+typedef struct {
+  int32_t n_boxes;            /* >= 1 */
+  int32_t chain_len;          /* atoms per chain, >= 4 */
+  const int32_t* n_chains;    /* host [n_boxes], >= 1 each */
+  const double* box;          /* host [n_boxes * 3], box edges in A */
+  const double* T0;           /* host [n_boxes], thermostat target in K; <= 0: NVE */
+  double dt_fs;               /* time step, fs (> 0) */
+  double tau_fs;              /* Berendsen coupling time, fs (> 0) */
+  int32_t precision;          /* md_precision */
+  int32_t cell_div;           /* R: cells of edge >= rc / R, (2R+1)^3 cells visited;
+                                 1 = the paper's grid (edge >= cutoff), 2 = half cells;
+                                 0 = chosen by the autotuner at init */
+  int32_t lj_kernel;          /* md_lj_kernel */
+  int32_t use_graph;          /* 1: md_step replays a captured hipGraph of the step */
+} md_config;
+
+/* Per-box results of the most recent energy evaluation. */
+typedef struct {
+  double e_lj;           /* truncated LJ energy, kcal/mol */
+  double e_lj_shifted;   /* sum over counted pairs of E(r) - E(rc) (reporting only) */
+  double e_bond, e_angle, e_dih;
+  double e_kin;          /* kinetic energy before thermostat scaling, kcal/mol */
+  double temperature;    /* K, 3N - 3 degrees of freedom */
+  double virial;         /* sum over interactions of r . F (LJ + bonded), kcal/mol */
+  int64_t step;          /* steps taken since init */
+} md_energy;
+
+typedef struct md_ctx md_ctx;
+
+/* Bytes of device workspace the configuration needs (for cell_div = 0 or
+   lj_kernel = 0, the largest over the autotuner's candidates).  Never fails for a
+   valid configuration; MD_ERR_ARG / MD_ERR_BOX_TOO_SMALL otherwise. */
+md_status md_workspace_bytes(const md_forcefield* ff, const md_config* cfg, size_t* bytes);
+
+/* Validates the configuration, copies the small per-box tables to the device,
+   builds the bins and computes the forces at the initial positions (so the first
+   half-kick has a force), and, when use_graph = 1, captures the step graph.
+   pos, vel: device FP64 [3 * N], updated in place by md_step.
+   type:     device uint8 [N], 0 or 1.
+   workspace: device, >= md_workspace_bytes, 256-byte aligned.
+   stream:   a hipStream_t (null = the default stream).
+   With cell_div = 0 or lj_kernel = 0 the autotuner times the candidates on these
+   inputs first (positions are not changed by it).  On success *out is a new context. */
+md_status md_init_system(const md_forcefield* ff, const md_config* cfg, double* pos, double* vel,
+                         const uint8_t* type, void* workspace, size_t ws_bytes, void* stream,
+                         md_ctx** out);
+
+/* Wrap positions into their box, recompute cell indices and rebuild the cell lists
+   and the sorted coordinate payload (Section 3.1). */
+md_status md_rebuild_bins(md_ctx* ctx);
+
+/* Forces at the positions of the last bin rebuild: LJ (Section 3.2) plus bonded
+   (Section 3.3); with_energy != 0 also evaluates the per-box energies and virial
+   (read them with md_energies). */
+md_status md_compute_forces(md_ctx* ctx, int32_t with_energy);
+
+/* Advance every box by n_steps (>= 0) velocity-Verlet steps with the bins rebuilt
+   every step; energies are evaluated on the last step.  Enqueues only. */
+md_status md_step(md_ctx* ctx, int32_t n_steps);
+
+/* Phases timed by md_step_timed. */
+enum {
+  MD_PHASE_INTEGRATE_BIN = 0,  /* lambda scaling, half kick, drift, wrap, cell index, count */
+  MD_PHASE_SCAN = 1,           /* exclusive scan of the cell counts */
+  MD_PHASE_SCATTER = 2,        /* unordered cell lists */
+  MD_PHASE_RANK = 3,           /* ordered cell lists and the sorted payload */
+  MD_PHASE_LJ = 4,             /* Lennard-Jones forces */
+  MD_PHASE_BONDED = 5,         /* bonded forces, total force, second half kick */
+  MD_PHASE_REDUCE = 6,         /* per-box sums and the thermostat factor */
+  MD_N_PHASES = 7
+};
+
+/* Same as md_step but launched without the graph and with a pair of HIP events
+   around every phase on the context's stream; adds each phase's summed duration in
+   milliseconds to ms_out[MD_N_PHASES].  Synchronises the stream before returning. */
+md_status md_step_timed(md_ctx* ctx, int32_t n_steps, double* ms_out);
+
+/* Synchronises the stream and copies the per-box results to out_host[n_boxes].
+   Returns MD_ERR_NONFINITE if the device flagged a non-finite value (sticky). */
+md_status md_energies(md_ctx* ctx, md_energy* out_host);
+
+/* Device views of the cell lists of the last rebuild: cell_start[n_cells + 1]
+   (exclusive prefix sums, cells of all boxes concatenated box by box) and
+   cell_atoms[N] (global atom indices, ascending within a cell). */
+md_status md_bins(md_ctx* ctx, const int32_t** cell_start, const int32_t** cell_atoms,
+                  int64_t* n_cells);
+
+/* Grid of one box: cells per dimension (cell index = kx + M[0] * (ky + M[1] * kz)),
+   and the offsets of its first cell and first atom in the concatenated arrays. */
+md_status md_grid(const md_ctx* ctx, int32_t box, int32_t M[3], int64_t* cell_offset,
+                  int64_t* atom_offset);
+
+/* Device view of the total force of the last evaluation, SoA [3 * N], FP32 when
+   *is_fp32 = 1 (mixed precision) else FP64; kcal/mol/A. */
+md_status md_forces(md_ctx* ctx, const void** f, int32_t* is_fp32);
+
+/* Device view of the LJ part of the force alone, same layout as md_forces. */
+md_status md_forces_lj(md_ctx* ctx, const void** f, int32_t* is_fp32);
+
+/* The stencil radius and LJ kernel in use (what the autotuner chose, if asked). */
+md_status md_tuning(const md_ctx* ctx, int32_t* cell_div, int32_t* lj_kernel);
+
+/* Frees the host-side context and its graph; device buffers stay with the caller. */
+md_status md_destroy(md_ctx* ctx);
+
+const char* md_status_string(md_status s);
+const char* md_last_error(const md_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,644 @@
+// C ABI of the gfx950 MD library: validation, workspace layout, step sequencing,
+// hipGraph capture and the autotuner.  Declarations and contracts: include/md.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "md.h"
+#include "md_internal.h"
+
+using namespace mdk;
+
+struct md_ctx {
+  md_forcefield ff{};
+  int32_t n_boxes = 0, chain_len = 0;
+  std::vector<int32_t> n_chains;
+  std::vector<double> box, T0;
+  double dt = 1.0, tau = 100.0;
+  int prec = MD_PREC_MIXED;
+  int R = 1, lj_kernel = MD_LJ_ATOM, use_graph = 0;
+  int64_t N = 0;
+  FFDev ffd{};
+  Views v{};
+  std::vector<BoxDev> hboxes;
+  double* pos = nullptr;
+  double* vel = nullptr;
+  const uint8_t* type = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  int64_t step = 0;
+  bool failed = false;
+  std::string last_error;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+md_status fail(md_ctx* c, md_status s, const std::string& msg) {
+  if (c) c->last_error = msg;
+  return s;
+}
+
+md_status hip_check(md_ctx* c, hipError_t e, const char* what) {
+  if (e == hipSuccess) return MD_OK;
+  return fail(c, MD_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0; }
+
+md_status validate(const md_forcefield* ff, const md_config* cfg, std::string* why) {
+  if (!ff || !cfg) { *why = "null forcefield or config"; return MD_ERR_ARG; }
+  for (int t = 0; t < 2; ++t)
+    if (!finite_pos(ff->mass[t]) || !finite_pos(ff->sigma[t]) || !(ff->epsilon[t] >= 0) ||
+        !std::isfinite(ff->epsilon[t])) {
+      *why = "mass/sigma must be > 0 and epsilon >= 0";
+      return MD_ERR_ARG;
+    }
+  if (!std::isfinite(ff->kb) || !std::isfinite(ff->ka) || !std::isfinite(ff->kphi) ||
+      !std::isfinite(ff->b0) || !std::isfinite(ff->theta0_deg) || !std::isfinite(ff->phis_deg) ||
+      !finite_pos(ff->rc) || ff->n_dih < 1 || ff->n_dih > 12 || ff->excl_depth < 0) {
+    *why = "bad bonded parameters, cutoff, periodicity or exclusion depth";
+    return MD_ERR_ARG;
+  }
+  if (cfg->n_boxes < 1 || cfg->chain_len < 4 || !cfg->n_chains || !cfg->box || !cfg->T0) {
+    *why = "n_boxes >= 1, chain_len >= 4 and the host arrays are required";
+    return MD_ERR_ARG;
+  }
+  if (ff->excl_depth >= cfg->chain_len) { *why = "excl_depth must be below chain_len"; return MD_ERR_ARG; }
+  if (!finite_pos(cfg->dt_fs) || !finite_pos(cfg->tau_fs)) { *why = "dt and tau must be > 0"; return MD_ERR_ARG; }
+  if (cfg->precision != MD_PREC_FP64 && cfg->precision != MD_PREC_MIXED) { *why = "bad precision"; return MD_ERR_ARG; }
+  if (cfg->cell_div < 0 || cfg->cell_div > 3) { *why = "cell_div must be 0..3"; return MD_ERR_ARG; }
+  if (cfg->lj_kernel < 0 || cfg->lj_kernel > 2) { *why = "lj_kernel must be 0..2"; return MD_ERR_ARG; }
+  int64_t N = 0;
+  for (int b = 0; b < cfg->n_boxes; ++b) {
+    if (cfg->n_chains[b] < 1) { *why = "every box needs at least one chain"; return MD_ERR_ARG; }
+    for (int d = 0; d < 3; ++d)
+      if (!finite_pos(cfg->box[3 * b + d])) { *why = "box edges must be > 0"; return MD_ERR_ARG; }
+    if (!std::isfinite(cfg->T0[b])) { *why = "T0 must be finite"; return MD_ERR_ARG; }
+    N += (int64_t)cfg->n_chains[b] * cfg->chain_len;
+  }
+  if (N < 2 || N > kMaxAtoms) { *why = "total atoms must be in [2, 2^27]"; return MD_ERR_ARG; }
+  return MD_OK;
+}
+
+int cells_per_dim(double L, int R, double rc) { return (int)std::floor(L * R / rc); }
+
+constexpr int64_t kMaxScanTiles = (int64_t)kScanBlock * 8;   // k_scan_top: 8 tiles per thread
+
+bool grid_ok(const md_forcefield* ff, const md_config* cfg, int R) {
+  int64_t cells = 0;
+  for (int b = 0; b < cfg->n_boxes; ++b) {
+    int64_t nc = 1;
+    for (int d = 0; d < 3; ++d) {
+      const int M = cells_per_dim(cfg->box[3 * b + d], R, ff->rc);
+      if (M < 2 * R + 1) return false;
+      nc *= M;
+    }
+    cells += nc;
+  }
+  return cells <= kMaxScanTiles * kScanTile && cells < ((int64_t)1 << 31);
+}
+
+struct Plan {
+  int64_t N = 0, C = 0;
+  int32_t n_boxes = 0, n_atom_blocks = 0, n_lj_blocks = 0, n_tiles = 0;
+  int prec = 0;
+  std::vector<BoxDev> boxes;
+};
+
+Plan make_plan(const md_forcefield* ff, const md_config* cfg, int R, int kernel) {
+  Plan p;
+  p.n_boxes = cfg->n_boxes;
+  p.prec = cfg->precision;
+  int64_t atom = 0, cell = 0, blk = 0, lblk = 0;
+  for (int b = 0; b < cfg->n_boxes; ++b) {
+    BoxDev B{};
+    const int64_t n = (int64_t)cfg->n_chains[b] * cfg->chain_len;
+    int64_t nc = 1;
+    for (int d = 0; d < 3; ++d) {
+      const double L = cfg->box[3 * b + d];
+      const int M = cells_per_dim(L, R, ff->rc);
+      B.L[d] = L;
+      B.invL[d] = 1.0 / L;
+      B.M[d] = M;
+      B.cinv[d] = (double)M / L;
+      B.edge[d] = L / (double)M;
+      nc *= M;
+    }
+    B.atom_off = (int32_t)atom;
+    B.n_atoms = (int32_t)n;
+    B.cell_off = (int32_t)cell;
+    B.n_cells = (int32_t)nc;
+    B.blk_off = (int32_t)blk;
+    B.lj_blk_off = (int32_t)lblk;
+    B.T0 = cfg->T0[b];
+    B.dof = (double)(3 * n - 3);
+    atom += n;
+    cell += nc;
+    blk += (n + kAtomBlock - 1) / kAtomBlock;
+    lblk += lj_blocks_for_box(kernel, n, nc);
+    p.boxes.push_back(B);
+  }
+  p.N = atom;
+  p.C = cell;
+  p.n_atom_blocks = (int32_t)blk;
+  p.n_lj_blocks = (int32_t)lblk;
+  p.n_tiles = (int32_t)((cell + kScanTile - 1) / kScanTile);
+  return p;
+}
+
+// Carves the workspace (base may be null to only measure).
+size_t carve(const Plan& p, char* base, Views* v) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* r = base ? base + off : nullptr;
+    off += align_up(bytes > 0 ? bytes : 1);
+    return r;
+  };
+  const size_t fsz = p.prec == MD_PREC_MIXED ? 4 : 8;
+  const size_t psz = p.prec == MD_PREC_MIXED ? 16 : 32;
+  Views t{};
+  t.N = p.N;
+  t.C = p.C;
+  t.n_boxes = p.n_boxes;
+  t.n_atom_blocks = p.n_atom_blocks;
+  t.n_lj_blocks = p.n_lj_blocks;
+  t.boxes = (const BoxDev*)take(sizeof(BoxDev) * p.n_boxes);
+  t.blk_box = (const int32_t*)take(4 * (size_t)p.n_atom_blocks);
+  t.lj_blk_box = (const int32_t*)take(4 * (size_t)p.n_lj_blocks);
+  t.cell = (int32_t*)take(4 * (size_t)p.N);
+  t.slot = (int32_t*)take(4 * (size_t)p.N);
+  t.cnt = (int32_t*)take(4 * (size_t)p.C);
+  t.cell_start = (int32_t*)take(4 * (size_t)(p.C + 1));
+  t.tmp = (int32_t*)take(4 * (size_t)p.N);
+  t.cell_atoms = (int32_t*)take(4 * (size_t)p.N);
+  t.scell = (int32_t*)take(4 * (size_t)p.N);
+  t.payload = take(psz * (size_t)p.N);
+  t.f_lj = take(3 * fsz * (size_t)p.N);
+  t.f_tot = take(3 * fsz * (size_t)p.N);
+  t.scan_tiles = (int32_t*)take(4 * (size_t)p.n_tiles);
+  t.part_lj = (dd*)take(sizeof(dd) * 3 * (size_t)p.n_lj_blocks);
+  t.part_bd = (dd*)take(sizeof(dd) * 5 * (size_t)p.n_atom_blocks);
+  t.lambda = (double*)take(8 * (size_t)p.n_boxes);
+  t.energy = (double*)take(64 * (size_t)p.n_boxes);
+  t.err = (int32_t*)take(4);
+  if (v) *v = t;
+  return off;
+}
+
+FFDev make_ffdev(const md_forcefield* ff, int chain_len) {
+  FFDev d{};
+  for (int t = 0; t < 2; ++t) {
+    d.acc_over_m[t] = kAccUnit / ff->mass[t];
+    d.half_m_over_acc[t] = 0.5 * ff->mass[t] / kAccUnit;
+  }
+  d.uniform_lj = 1;
+  for (int ti = 0; ti < 2; ++ti)
+    for (int tj = 0; tj < 2; ++tj) {
+      const int t = ti * 2 + tj;
+      const double sig = 0.5 * (ff->sigma[ti] + ff->sigma[tj]);   // Lorentz-Berthelot
+      const double eps = std::sqrt(ff->epsilon[ti] * ff->epsilon[tj]);
+      const double s6 = sig * sig * sig * sig * sig * sig;
+      const double ljp1 = 4.0 * eps * s6;          // 4 eps sigma^6
+      const double ljp2 = 4.0 * eps * s6 * s6;     // 4 eps sigma^12
+      d.e12[t] = ljp2;
+      d.e6[t] = ljp1;
+      d.f12[t] = 12.0 * ljp2;
+      d.f6[t] = 6.0 * ljp1;
+      const double rc6 = std::pow(ff->rc, 6.0);
+      d.ecut[t] = ljp2 / (rc6 * rc6) - ljp1 / rc6;
+    }
+  for (int t = 1; t < 4; ++t)
+    if (d.f12[t] != d.f12[0] || d.f6[t] != d.f6[0]) d.uniform_lj = 0;
+  d.rc2 = ff->rc * ff->rc;
+  d.kb = ff->kb;
+  d.b0 = ff->b0;
+  d.ka = ff->ka;
+  d.theta0 = ff->theta0_deg * M_PI / 180.0;
+  d.kphi = ff->kphi;
+  d.cos_phis = std::cos(ff->phis_deg * M_PI / 180.0);
+  d.sin_phis = std::sin(ff->phis_deg * M_PI / 180.0);
+  d.n_dih = ff->n_dih;
+  d.excl = ff->excl_depth;
+  d.chain_len = chain_len;
+  return d;
+}
+
+md_status check_launch(md_ctx* c, const char* what) { return hip_check(c, hipGetLastError(), what); }
+
+// Lays out the workspace for stencil radius R and kernel k, uploads the tables and
+// clears the counters.  Does not touch positions or velocities.
+md_status configure(md_ctx* c, const md_config* cfg, int R, int kernel) {
+  Plan p = make_plan(&c->ff, cfg, R, kernel);
+  Views v{};
+  const size_t need = carve(p, nullptr, nullptr);
+  if (need > c->ws_bytes) return fail(c, MD_ERR_WORKSPACE, "workspace too small for this configuration");
+  carve(p, c->ws, &v);
+  v.R = R;
+  v.pos = c->pos;
+  v.vel = c->vel;
+  v.type = c->type;
+  std::vector<int32_t> bb(p.n_atom_blocks), lb(p.n_lj_blocks);
+  for (int b = 0; b < p.n_boxes; ++b) {
+    const int32_t e1 = b + 1 < p.n_boxes ? p.boxes[b + 1].blk_off : p.n_atom_blocks;
+    for (int32_t k = p.boxes[b].blk_off; k < e1; ++k) bb[k] = b;
+    const int32_t e2 = b + 1 < p.n_boxes ? p.boxes[b + 1].lj_blk_off : p.n_lj_blocks;
+    for (int32_t k = p.boxes[b].lj_blk_off; k < e2; ++k) lb[k] = b;
+  }
+  md_status st;
+  // pageable sources: hipMemcpy (synchronous) so the host vectors may go away
+  if ((st = hip_check(c, hipStreamSynchronize(c->stream), "sync"))) return st;
+  if ((st = hip_check(c, hipMemcpy((void*)v.boxes, p.boxes.data(), sizeof(BoxDev) * p.n_boxes,
+                                   hipMemcpyHostToDevice), "upload boxes")))
+    return st;
+  if ((st = hip_check(c, hipMemcpy((void*)v.blk_box, bb.data(), 4 * bb.size(), hipMemcpyHostToDevice),
+                      "upload block table")))
+    return st;
+  if ((st = hip_check(c, hipMemcpy((void*)v.lj_blk_box, lb.data(), 4 * lb.size(), hipMemcpyHostToDevice),
+                      "upload LJ block table")))
+    return st;
+  launch_fill_i32(v.cnt, p.C, 0, c->stream);
+  launch_fill_i32(v.err, 1, 0, c->stream);
+  launch_fill_f64(v.lambda, p.n_boxes, 1.0, c->stream);
+  launch_fill_f64(v.energy, 8 * (int64_t)p.n_boxes, 0.0, c->stream);
+  if ((st = check_launch(c, "clear workspace"))) return st;
+  c->v = v;
+  c->hboxes = p.boxes;
+  c->R = R;
+  c->lj_kernel = kernel;
+  return MD_OK;
+}
+
+void enqueue_rebuild(md_ctx* c, hipStream_t s, bool kick) {
+  const bool fp32 = c->prec == MD_PREC_MIXED;
+  launch_bin_count(c->v, kick, c->dt, c->ffd, fp32, s);
+  launch_scan(c->v, s);
+  launch_scatter(c->v, s);
+  launch_rank_payload(c->v, fp32, s);
+}
+
+void enqueue_forces(md_ctx* c, hipStream_t s, bool kick, bool energy) {
+  const bool fp32 = c->prec == MD_PREC_MIXED;
+  launch_lj(c->v, c->ffd, fp32, c->lj_kernel, energy, s);
+  launch_bonded(c->v, c->ffd, fp32, kick, energy, c->dt, s);
+}
+
+void enqueue_step(md_ctx* c, hipStream_t s, bool energy) {
+  enqueue_rebuild(c, s, true);
+  enqueue_forces(c, s, true, energy);
+  launch_reduce(c->v, energy, true, c->dt, c->tau, s);
+}
+
+void destroy_graphs(md_ctx* c) {
+  for (int k = 0; k < 2; ++k) {
+    if (c->exec[k]) (void)hipGraphExecDestroy(c->exec[k]);
+    if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
+    c->exec[k] = nullptr;
+    c->graph[k] = nullptr;
+  }
+}
+
+md_status capture_graphs(md_ctx* c) {
+  destroy_graphs(c);
+  md_status st;
+  if (!c->cap && (st = hip_check(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking), "capture stream")))
+    return st;
+  for (int k = 0; k < 2; ++k) {
+    if ((st = hip_check(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal), "begin capture")))
+      return st;
+    enqueue_step(c, c->cap, k == 1);
+    hipError_t le = hipGetLastError();
+    hipError_t e = hipStreamEndCapture(c->cap, &c->graph[k]);
+    if ((st = hip_check(c, le, "launch during capture"))) return st;
+    if ((st = hip_check(c, e, "end capture"))) return st;
+    if ((st = hip_check(c, hipGraphInstantiate(&c->exec[k], c->graph[k], nullptr, nullptr, 0),
+                        "instantiate graph")))
+      return st;
+  }
+  return MD_OK;
+}
+
+// Times rebuild + forces for each candidate and keeps the fastest.
+md_status autotune(md_ctx* c, const md_config* cfg, int* bestR, int* bestK) {
+  std::vector<int> Rs, Ks;
+  if (cfg->cell_div) Rs.push_back(cfg->cell_div);
+  else
+    for (int R = 1; R <= 2; ++R)
+      if (grid_ok(&c->ff, cfg, R)) Rs.push_back(R);
+  if (cfg->lj_kernel) Ks.push_back(cfg->lj_kernel);
+  else
+    Ks.push_back(MD_LJ_ATOM);
+  if (Rs.empty()) return fail(c, MD_ERR_BOX_TOO_SMALL, "no stencil fits every box");
+  hipEvent_t e0, e1;
+  md_status st;
+  if ((st = hip_check(c, hipEventCreate(&e0), "event"))) return st;
+  if ((st = hip_check(c, hipEventCreate(&e1), "event"))) return st;
+  float best = 1e30f;
+  *bestR = Rs[0];
+  *bestK = Ks[0];
+  for (int R : Rs)
+    for (int K : Ks) {
+      if (Rs.size() * Ks.size() == 1) break;
+      if ((st = configure(c, cfg, R, K))) break;
+      enqueue_rebuild(c, c->stream, false);
+      enqueue_forces(c, c->stream, false, false);
+      (void)hipEventRecord(e0, c->stream);
+      for (int rep = 0; rep < 3; ++rep) {
+        enqueue_rebuild(c, c->stream, false);
+        enqueue_forces(c, c->stream, false, false);
+      }
+      (void)hipEventRecord(e1, c->stream);
+      if ((st = hip_check(c, hipEventSynchronize(e1), "autotune sync"))) break;
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) {
+        best = ms;
+        *bestR = R;
+        *bestK = K;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+md_status md_workspace_bytes(const md_forcefield* ff, const md_config* cfg, size_t* bytes) {
+  std::string why;
+  if (!bytes) return MD_ERR_ARG;
+  md_status st = validate(ff, cfg, &why);
+  if (st) return st;
+  size_t best = 0;
+  bool any = false;
+  for (int R = 1; R <= 3; ++R) {
+    if (cfg->cell_div && cfg->cell_div != R) continue;
+    if (!cfg->cell_div && R > 2) continue;
+    if (!grid_ok(ff, cfg, R)) continue;
+    for (int K = 1; K <= 2; ++K) {
+      if (cfg->lj_kernel && cfg->lj_kernel != K) continue;
+      best = std::max(best, carve(make_plan(ff, cfg, R, K), nullptr, nullptr));
+      any = true;
+    }
+  }
+  if (!any) return MD_ERR_BOX_TOO_SMALL;
+  *bytes = best;
+  return MD_OK;
+}
+
+md_status md_init_system(const md_forcefield* ff, const md_config* cfg, double* pos, double* vel,
+                         const uint8_t* type, void* workspace, size_t ws_bytes, void* stream,
+                         md_ctx** out) {
+  if (!out) return MD_ERR_ARG;
+  *out = nullptr;
+  std::string why;
+  md_status st = validate(ff, cfg, &why);
+  if (st) return st;
+  if (!pos || !vel || !type || !workspace) return MD_ERR_ARG;
+  if (((uintptr_t)workspace) % kAlign) return MD_ERR_WORKSPACE;
+  if (cfg->cell_div && !grid_ok(ff, cfg, cfg->cell_div)) return MD_ERR_BOX_TOO_SMALL;
+  if (!cfg->cell_div && !grid_ok(ff, cfg, 1)) return MD_ERR_BOX_TOO_SMALL;
+  if (cfg->lj_kernel == MD_LJ_CELLTILE) return MD_ERR_ARG;   // not available in this build
+  size_t need = 0;
+  if ((st = md_workspace_bytes(ff, cfg, &need))) return st;
+  if (ws_bytes < need) return MD_ERR_WORKSPACE;
+  md_ctx* c = new (std::nothrow) md_ctx();
+  if (!c) return MD_ERR_ARG;
+  c->ff = *ff;
+  c->n_boxes = cfg->n_boxes;
+  c->chain_len = cfg->chain_len;
+  c->n_chains.assign(cfg->n_chains, cfg->n_chains + cfg->n_boxes);
+  c->box.assign(cfg->box, cfg->box + 3 * cfg->n_boxes);
+  c->T0.assign(cfg->T0, cfg->T0 + cfg->n_boxes);
+  c->dt = cfg->dt_fs;
+  c->tau = cfg->tau_fs;
+  c->prec = cfg->precision;
+  c->use_graph = cfg->use_graph ? 1 : 0;
+  c->pos = pos;
+  c->vel = vel;
+  c->type = type;
+  c->ws = (char*)workspace;
+  c->ws_bytes = ws_bytes;
+  c->stream = (hipStream_t)stream;
+  c->ffd = make_ffdev(ff, cfg->chain_len);
+  md_config local = *cfg;
+  local.n_chains = c->n_chains.data();
+  local.box = c->box.data();
+  local.T0 = c->T0.data();
+  int R = cfg->cell_div ? cfg->cell_div : 1;
+  int K = cfg->lj_kernel ? cfg->lj_kernel : MD_LJ_ATOM;
+  if (!cfg->cell_div || !cfg->lj_kernel) st = autotune(c, &local, &R, &K);
+  if (!st) st = configure(c, &local, R, K);
+  if (!st) {
+    enqueue_rebuild(c, c->stream, false);
+    enqueue_forces(c, c->stream, false, true);
+    launch_reduce(c->v, true, false, c->dt, c->tau, c->stream);
+    st = check_launch(c, "initial forces");
+  }
+  if (!st && c->use_graph) st = capture_graphs(c);
+  if (!st) st = hip_check(c, hipStreamSynchronize(c->stream), "init sync");
+  if (st) {
+    std::fprintf(stderr, "md_init_system: %s\n", c->last_error.c_str());
+    destroy_graphs(c);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
+    delete c;
+    return st;
+  }
+  *out = c;
+  return MD_OK;
+}
+
+md_status md_rebuild_bins(md_ctx* c) {
+  if (!c) return MD_ERR_ARG;
+  if (c->failed) return MD_ERR_STATE;
+  enqueue_rebuild(c, c->stream, false);
+  return check_launch(c, "rebuild bins");
+}
+
+md_status md_compute_forces(md_ctx* c, int32_t with_energy) {
+  if (!c) return MD_ERR_ARG;
+  if (c->failed) return MD_ERR_STATE;
+  enqueue_forces(c, c->stream, false, with_energy != 0);
+  if (with_energy) launch_reduce(c->v, true, false, c->dt, c->tau, c->stream);
+  return check_launch(c, "compute forces");
+}
+
+md_status md_step(md_ctx* c, int32_t n_steps) {
+  if (!c || n_steps < 0) return MD_ERR_ARG;
+  if (c->failed) return MD_ERR_STATE;
+  if (n_steps == 0) return MD_OK;
+  md_status st;
+  for (int32_t k = 0; k < n_steps; ++k) {
+    const bool last = k == n_steps - 1;
+    if (c->use_graph) {
+      if ((st = hip_check(c, hipGraphLaunch(c->exec[last ? 1 : 0], c->stream), "graph launch"))) return st;
+    } else {
+      enqueue_step(c, c->stream, last);
+    }
+  }
+  launch_finalize(c->v, c->stream);
+  c->step += n_steps;
+  return check_launch(c, "step");
+}
+
+md_status md_step_timed(md_ctx* c, int32_t n_steps, double* ms_out) {
+  if (!c || n_steps < 0 || !ms_out) return MD_ERR_ARG;
+  if (c->failed) return MD_ERR_STATE;
+  if (n_steps == 0) return MD_OK;
+  md_status st;
+  const int P = MD_N_PHASES;
+  std::vector<hipEvent_t> ev((size_t)n_steps * P * 2, nullptr);
+  for (auto& e : ev)
+    if ((st = hip_check(c, hipEventCreate(&e), "event create"))) {
+      for (auto& x : ev)
+        if (x) (void)hipEventDestroy(x);
+      return st;
+    }
+  const bool fp32 = c->prec == MD_PREC_MIXED;
+  hipStream_t s = c->stream;
+  for (int32_t k = 0; k < n_steps; ++k) {
+    const bool last = k == n_steps - 1;
+    hipEvent_t* e = &ev[(size_t)k * P * 2];
+    (void)hipEventRecord(e[0], s);
+    launch_bin_count(c->v, true, c->dt, c->ffd, fp32, s);
+    (void)hipEventRecord(e[1], s);
+    (void)hipEventRecord(e[2], s);
+    launch_scan(c->v, s);
+    (void)hipEventRecord(e[3], s);
+    (void)hipEventRecord(e[4], s);
+    launch_scatter(c->v, s);
+    (void)hipEventRecord(e[5], s);
+    (void)hipEventRecord(e[6], s);
+    launch_rank_payload(c->v, fp32, s);
+    (void)hipEventRecord(e[7], s);
+    (void)hipEventRecord(e[8], s);
+    launch_lj(c->v, c->ffd, fp32, c->lj_kernel, last, s);
+    (void)hipEventRecord(e[9], s);
+    (void)hipEventRecord(e[10], s);
+    launch_bonded(c->v, c->ffd, fp32, true, last, c->dt, s);
+    (void)hipEventRecord(e[11], s);
+    (void)hipEventRecord(e[12], s);
+    launch_reduce(c->v, last, true, c->dt, c->tau, s);
+    (void)hipEventRecord(e[13], s);
+  }
+  launch_finalize(c->v, s);
+  c->step += n_steps;
+  st = check_launch(c, "timed step");
+  if (!st) st = hip_check(c, hipStreamSynchronize(s), "timed step sync");
+  if (!st)
+    for (int32_t k = 0; k < n_steps; ++k)
+      for (int p = 0; p < P; ++p) {
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, ev[((size_t)k * P + p) * 2], ev[((size_t)k * P + p) * 2 + 1]);
+        ms_out[p] += ms;
+      }
+  for (auto& x : ev) (void)hipEventDestroy(x);
+  return st;
+}
+
+md_status md_energies(md_ctx* c, md_energy* out) {
+  if (!c || !out) return MD_ERR_ARG;
+  md_status st;
+  if ((st = hip_check(c, hipStreamSynchronize(c->stream), "sync"))) return st;
+  std::vector<double> e(8 * (size_t)c->n_boxes);
+  int32_t err = 0;
+  if ((st = hip_check(c, hipMemcpy(e.data(), c->v.energy, 8 * e.size(), hipMemcpyDeviceToHost), "read energies")))
+    return st;
+  if ((st = hip_check(c, hipMemcpy(&err, c->v.err, 4, hipMemcpyDeviceToHost), "read error word"))) return st;
+  for (int b = 0; b < c->n_boxes; ++b) {
+    const double* q = &e[8 * (size_t)b];
+    out[b].e_lj = q[0];
+    out[b].e_lj_shifted = q[1];
+    out[b].e_bond = q[2];
+    out[b].e_angle = q[3];
+    out[b].e_dih = q[4];
+    out[b].e_kin = q[5];
+    out[b].temperature = q[6];
+    out[b].virial = q[7];
+    out[b].step = c->step;
+  }
+  if (err & kErrNonFinite) {
+    c->failed = true;
+    return fail(c, MD_ERR_NONFINITE, "a position became non-finite");
+  }
+  return MD_OK;
+}
+
+md_status md_bins(md_ctx* c, const int32_t** cell_start, const int32_t** cell_atoms, int64_t* n_cells) {
+  if (!c || !cell_start || !cell_atoms || !n_cells) return MD_ERR_ARG;
+  *cell_start = c->v.cell_start;
+  *cell_atoms = c->v.cell_atoms;
+  *n_cells = c->v.C;
+  return MD_OK;
+}
+
+md_status md_grid(const md_ctx* c, int32_t box, int32_t M[3], int64_t* cell_offset, int64_t* atom_offset) {
+  if (!c || !M || box < 0 || box >= c->n_boxes) return MD_ERR_ARG;
+  const BoxDev& B = c->hboxes[box];
+  for (int d = 0; d < 3; ++d) M[d] = B.M[d];
+  if (cell_offset) *cell_offset = B.cell_off;
+  if (atom_offset) *atom_offset = B.atom_off;
+  return MD_OK;
+}
+
+md_status md_forces(md_ctx* c, const void** f, int32_t* is_fp32) {
+  if (!c || !f || !is_fp32) return MD_ERR_ARG;
+  *f = c->v.f_tot;
+  *is_fp32 = c->prec == MD_PREC_MIXED;
+  return MD_OK;
+}
+
+md_status md_forces_lj(md_ctx* c, const void** f, int32_t* is_fp32) {
+  if (!c || !f || !is_fp32) return MD_ERR_ARG;
+  *f = c->v.f_lj;
+  *is_fp32 = c->prec == MD_PREC_MIXED;
+  return MD_OK;
+}
+
+md_status md_tuning(const md_ctx* c, int32_t* cell_div, int32_t* lj_kernel) {
+  if (!c || !cell_div || !lj_kernel) return MD_ERR_ARG;
+  *cell_div = c->R;
+  *lj_kernel = c->lj_kernel;
+  return MD_OK;
+}
+
+md_status md_destroy(md_ctx* c) {
+  if (!c) return MD_ERR_ARG;
+  (void)hipStreamSynchronize(c->stream);
+  destroy_graphs(c);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
+  delete c;
+  return MD_OK;
+}
+
+const char* md_status_string(md_status s) {
+  switch (s) {
+    case MD_OK: return "ok";
+    case MD_ERR_ARG: return "invalid argument";
+    case MD_ERR_BOX_TOO_SMALL: return "box too small for the cell stencil";
+    case MD_ERR_NONFINITE: return "non-finite position or force";
+    case MD_ERR_WORKSPACE: return "workspace too small or misaligned";
+    case MD_ERR_HIP: return "HIP runtime error";
+    case MD_ERR_STATE: return "context in error state";
+  }
+  return "unknown status";
+}
+
+const char* md_last_error(const md_ctx* c) { return c ? c->last_error.c_str() : ""; }
+
+}  // extern "C"

@@ -1,0 +1,118 @@
+// Internal declarations of the gfx950 MD library (device structs, launchers).
+// Not part of the C ABI; see include/md.h for the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace mdk {
+
+constexpr int kAtomBlock = 256;   // threads per block of every per-atom kernel
+constexpr int kLjAtomBlock = 128; // threads per block of the lane-per-atom LJ kernel
+constexpr int kScanItems = 4;     // cells per thread in the scan
+constexpr int kScanBlock = 1024;
+constexpr int kScanTile = kScanItems * kScanBlock;
+constexpr int kHalo = 3;          // a dihedral reaches 3 atoms beyond its first atom
+
+// acceleration of 1 kcal/mol/A on 1 g/mol, in A/fs^2; gas constant in kcal/mol/K
+constexpr double kAccUnit = 4.184e-4;
+constexpr double kRgas = 1.987204259e-3;
+
+// tag of a sorted atom: global index << 4 | type << 3 | (cell x-index & 7)
+__host__ __device__ inline int32_t tag_index(int32_t tag) { return tag >> 4; }
+__host__ __device__ inline int32_t tag_type(int32_t tag) { return (tag >> 3) & 1; }
+__host__ __device__ inline int32_t tag_cx(int32_t tag) { return tag & 7; }
+constexpr int64_t kMaxAtoms = (int64_t)1 << 27;
+
+struct BoxDev {
+  double L[3], invL[3];   // edges and 1/L (computed on the host)
+  double cinv[3];         // M/L: cell index scale
+  double edge[3];         // L/M
+  int32_t M[3];
+  int32_t atom_off, n_atoms;
+  int32_t cell_off, n_cells;
+  int32_t blk_off;        // first per-atom block (kAtomBlock) of this box
+  int32_t lj_blk_off;     // first LJ work block of this box
+  int32_t pad;
+  double T0;              // <= 0: no thermostat
+  double dof;             // 3N - 3
+};
+
+// Force-field constants in the form the kernels use (built on the host).
+struct FFDev {
+  double acc_over_m[2];   // kAccUnit / mass
+  double half_m_over_acc[2];  // m / (2 kAccUnit): kinetic energy factor
+  // LJ per type pair t = ti * 2 + tj:
+  //   force scalar  ff = r^-2 r^-6 (f12 r^-6 - f6)   (F_i = ff * (x_i - x_j))
+  //   energy        E  = r^-6 (e12 r^-6 - e6)
+  double f12[4], f6[4], e12[4], e6[4], ecut[4];
+  double rc2;
+  double kb, b0, ka, theta0, kphi, cos_phis, sin_phis;
+  int32_t n_dih, excl, chain_len, uniform_lj;
+};
+
+// double-double accumulator (sum and the rounding error carried alongside)
+struct dd {
+  double hi, lo;
+};
+
+__device__ inline dd dd_add(dd a, dd b) {
+  double s = a.hi + b.hi;
+  double bb = s - a.hi;
+  double err = (a.hi - (s - bb)) + (b.hi - bb);
+  return dd{s, err + (a.lo + b.lo)};
+}
+__device__ inline dd dd_from(double v) { return dd{v, 0.0}; }
+
+// The views every launcher needs.
+struct Views {
+  int64_t N, C;            // atoms, cells (all boxes)
+  int32_t n_boxes, R;
+  int32_t n_atom_blocks, n_lj_blocks;
+  const BoxDev* boxes;
+  const int32_t* blk_box;      // [n_atom_blocks] box of each per-atom block
+  const int32_t* lj_blk_box;   // [n_lj_blocks] box of each LJ work block
+  double* pos;
+  double* vel;
+  const uint8_t* type;
+  int32_t* cell;       // [N] global cell of each atom
+  int32_t* slot;       // [N] arrival order within the cell (atomic)
+  int32_t* cnt;        // [C]
+  int32_t* cell_start; // [C + 1]
+  int32_t* tmp;        // [N] unordered cell lists
+  int32_t* cell_atoms; // [N] ordered cell lists
+  int32_t* scell;      // [N] cell of each sorted slot
+  void* payload;       // [N] float4 (mixed) / double4 (fp64), cell-centre-relative xyz + tag
+  void* f_lj;          // [3N] LJ force, prec
+  void* f_tot;         // [3N] total force, prec
+  int32_t* scan_tiles; // [n_tiles]
+  dd* part_lj;         // [n_lj_blocks * 3]: E_lj, E_lj_shifted, W_lj
+  dd* part_bd;         // [n_atom_blocks * 5]: E_b, E_a, E_d, W_b, KE
+  double* lambda;      // [n_boxes] pending Berendsen factor
+  double* energy;      // [n_boxes * 8] per-box results
+  int32_t* err;        // sticky error word
+};
+
+enum ErrBits : int32_t { kErrNonFinite = 1 };
+
+// ---- launchers (md_kernels.hip) ----
+void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+void launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
+void launch_bin_count(const Views& v, bool kick, double dt, const FFDev& ff, bool fp32_force,
+                      hipStream_t s);
+void launch_scan(const Views& v, hipStream_t s);
+void launch_scatter(const Views& v, hipStream_t s);
+void launch_rank_payload(const Views& v, bool fp32, hipStream_t s);
+void launch_bonded(const Views& v, const FFDev& ff, bool fp32, bool kick, bool energy, double dt,
+                   hipStream_t s);
+void launch_reduce(const Views& v, bool energy, bool thermostat, double dt, double tau,
+                   hipStream_t s);
+void launch_finalize(const Views& v, hipStream_t s);
+
+// ---- launchers (md_lj.hip) ----
+void launch_lj(const Views& v, const FFDev& ff, bool fp32, int kernel, bool energy, hipStream_t s);
+int64_t lj_blocks_for_box(int kernel, int64_t n_atoms, int64_t n_cells);
+
+}  // namespace mdk

@@ -1,0 +1,621 @@
+// Bin rebuild, bonded forces, integration and reductions for gfx950 (wave64).
+//
+// Bin rebuild (Section 3.1; the paper's atomic insertion gives each atom a slot in
+// its cell but an unspecified order -- here that slot is followed by a rank pass so
+// the cell lists come out in ascending atom order, the same every run):
+//   k_bin_count     wrap, cell index, slot = atomic count (one atomic per distinct
+//                   cell per wavefront, lanes ranked with ballot/popcount)
+//   k_scan_*        cell_start = exclusive prefix sum of the counts (three passes)
+//   k_scatter       unordered lists: tmp[cell_start[c] + slot] = atom
+//   k_rank_payload  rank inside the cell = number of smaller atom indices in it;
+//                   writes the ordered list and the cell-centre-relative payload
+// Bonded terms (Section 3.3, Eqs. 4-6): each term is computed once by one lane, its
+// per-atom forces go to LDS, and every atom gathers the terms touching it in a fixed
+// order (no doubled/tripled/quadrupled work, no atomics, bitwise reproducible).
+// Update (Section 3.4): velocity Verlet half-kicks and drift in FP64, Berendsen
+// scaling from the per-box kinetic energy, all sums as double-double.
+#include "md_internal.h"
+
+namespace mdk {
+namespace {
+
+struct alignas(32) Pay64 {
+  double x, y, z, tagbits;
+};
+
+__device__ inline double wrap_coord(double x, double L, double invL) {
+  if (x >= 0.0 && x < L) return x;
+  double s = floor(x * invL);
+  double y = fma(-s, L, x);
+  if (y >= L) y -= L;
+  if (y < 0.0) y += L;
+  return y;
+}
+
+__device__ inline int cell_coord(double x, double cinv, int M) {
+  double f = floor(x * cinv);
+  if (f < 0.0) return 0;
+  if (f > (double)(M - 1)) return M - 1;
+  return (int)f;
+}
+
+__device__ inline int lane() { return (int)(threadIdx.x & 63); }
+
+// Slot of this lane's atom inside its cell: one atomic per distinct cell in the
+// wavefront; lanes sharing a cell are ranked by lane order (ballot + popcount).
+__device__ inline int aggregated_slot(int32_t* cnt, int c, bool active) {
+  uint64_t pending = __ballot(active);
+  int my = 0;
+  const int ln = lane();
+  while (pending) {
+    const int leader = __ffsll((unsigned long long)pending) - 1;
+    const int lc = __shfl(c, leader);
+    const uint64_t grp = __ballot(active && c == lc);
+    int base = 0;
+    if (ln == leader) base = atomicAdd(&cnt[lc], __popcll(grp));
+    base = __shfl(base, leader);
+    if (active && c == lc) my = base + __popcll(grp & ((1ull << ln) - 1ull));
+    pending &= ~grp;
+  }
+  return my;
+}
+
+template <typename F, bool KICK>
+__global__ __launch_bounds__(kAtomBlock) void k_bin_count(Views v, const F* __restrict__ f, double dt,
+                                                        FFDev ff) {
+  const int b = v.blk_box[blockIdx.x];
+  const BoxDev& B = v.boxes[b];
+  const int local = ((int)blockIdx.x - B.blk_off) * kAtomBlock + (int)threadIdx.x;
+  const bool active = local < B.n_atoms;
+  const int64_t N = v.N;
+  const int64_t i = (int64_t)B.atom_off + local;
+  int c = 0;
+  if (active) {
+    double x = v.pos[i], y = v.pos[N + i], z = v.pos[2 * N + i];
+    bool moved = false;
+    if (KICK) {
+      const double lam = v.lambda[b];
+      const double h = 0.5 * dt * ff.acc_over_m[v.type[i]];
+      const double vx = lam * v.vel[i] + h * (double)f[i];
+      const double vy = lam * v.vel[N + i] + h * (double)f[N + i];
+      const double vz = lam * v.vel[2 * N + i] + h * (double)f[2 * N + i];
+      v.vel[i] = vx;
+      v.vel[N + i] = vy;
+      v.vel[2 * N + i] = vz;
+      x += dt * vx;
+      y += dt * vy;
+      z += dt * vz;
+      moved = true;
+    }
+    if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
+      atomicOr(v.err, (int)kErrNonFinite);
+      x = y = z = 0.0;   // keep every index in range; the run is already invalid
+      moved = true;
+    }
+    const double wx = wrap_coord(x, B.L[0], B.invL[0]);
+    const double wy = wrap_coord(y, B.L[1], B.invL[1]);
+    const double wz = wrap_coord(z, B.L[2], B.invL[2]);
+    if (moved || wx != x || wy != y || wz != z) {
+      v.pos[i] = wx;
+      v.pos[N + i] = wy;
+      v.pos[2 * N + i] = wz;
+    }
+    const int kx = cell_coord(wx, B.cinv[0], B.M[0]);
+    const int ky = cell_coord(wy, B.cinv[1], B.M[1]);
+    const int kz = cell_coord(wz, B.cinv[2], B.M[2]);
+    c = B.cell_off + kx + B.M[0] * (ky + B.M[1] * kz);
+    v.cell[i] = c;
+  }
+  const int s = aggregated_slot(v.cnt, c, active);
+  if (active) v.slot[i] = s;
+}
+
+// ---- exclusive scan of the counts ----
+__device__ int block_exclusive_scan(int val, int* sh, int* total) {
+  const int ln = lane(), w = (int)threadIdx.x >> 6;
+  const int nw = (int)blockDim.x >> 6;
+  int inc = val;
+  for (int d = 1; d < 64; d <<= 1) {
+    int t = __shfl_up(inc, d, 64);
+    if (ln >= d) inc += t;
+  }
+  if (ln == 63) sh[w] = inc;
+  __syncthreads();
+  if (w == 0) {
+    int x = ln < nw ? sh[ln] : 0;
+    int xi = x;
+    for (int d = 1; d < 64; d <<= 1) {
+      int t = __shfl_up(xi, d, 64);
+      if (ln >= d) xi += t;
+    }
+    if (ln < nw) sh[ln] = xi - x;
+    if (ln == nw - 1) sh[32] = xi;
+  }
+  __syncthreads();
+  const int ex = sh[w] + inc - val;
+  *total = sh[32];
+  __syncthreads();
+  return ex;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_tiles(const int32_t* __restrict__ cnt, int64_t C,
+                                                          int32_t* tiles) {
+  __shared__ int sh[33];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  int s = 0;
+  for (int k = 0; k < kScanItems; ++k)
+    if (base + k < C) s += cnt[base + k];
+  int total;
+  block_exclusive_scan(s, sh, &total);
+  if (threadIdx.x == 0) tiles[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_top(int32_t* tiles, int n_tiles, int32_t* cell_start,
+                                                        int64_t C) {
+  __shared__ int sh[33];
+  constexpr int kPer = 8;   // up to kScanBlock * 8 tiles
+  int vals[kPer];
+  int s = 0;
+  for (int k = 0; k < kPer; ++k) {
+    const int t = (int)threadIdx.x * kPer + k;
+    vals[k] = t < n_tiles ? tiles[t] : 0;
+    s += vals[k];
+  }
+  int total;
+  int ex = block_exclusive_scan(s, sh, &total);
+  for (int k = 0; k < kPer; ++k) {
+    const int t = (int)threadIdx.x * kPer + k;
+    if (t < n_tiles) tiles[t] = ex;
+    ex += vals[k];
+  }
+  if (threadIdx.x == 0) cell_start[C] = total;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_apply(int32_t* __restrict__ cnt, int64_t C,
+                                                          const int32_t* __restrict__ tiles,
+                                                          int32_t* __restrict__ cell_start) {
+  __shared__ int sh[33];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  int vals[kScanItems];
+  int s = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    vals[k] = base + k < C ? cnt[base + k] : 0;
+    s += vals[k];
+  }
+  int total;
+  int ex = block_exclusive_scan(s, sh, &total) + tiles[blockIdx.x];
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < C) {
+      cell_start[base + k] = ex;
+      cnt[base + k] = 0;   // ready for the next count
+    }
+    ex += vals[k];
+  }
+}
+
+__global__ __launch_bounds__(kAtomBlock) void k_scatter(Views v) {
+  const int b = v.blk_box[blockIdx.x];
+  const BoxDev& B = v.boxes[b];
+  const int local = ((int)blockIdx.x - B.blk_off) * kAtomBlock + (int)threadIdx.x;
+  if (local >= B.n_atoms) return;
+  const int64_t i = (int64_t)B.atom_off + local;
+  v.tmp[v.cell_start[v.cell[i]] + v.slot[i]] = (int32_t)i;
+}
+
+template <typename PayT>
+__device__ inline void store_payload(PayT* p, int64_t dst, double rx, double ry, double rz, int32_t tag);
+
+template <>
+__device__ inline void store_payload<float4>(float4* p, int64_t dst, double rx, double ry, double rz,
+                                             int32_t tag) {
+  p[dst] = make_float4((float)rx, (float)ry, (float)rz, __int_as_float(tag));
+}
+template <>
+__device__ inline void store_payload<Pay64>(Pay64* p, int64_t dst, double rx, double ry, double rz,
+                                            int32_t tag) {
+  Pay64 q;
+  q.x = rx;
+  q.y = ry;
+  q.z = rz;
+  q.tagbits = __longlong_as_double((long long)tag);
+  p[dst] = q;
+}
+
+template <typename PayT>
+__global__ __launch_bounds__(kAtomBlock) void k_rank_payload(Views v) {
+  const int b = v.blk_box[blockIdx.x];
+  const BoxDev& B = v.boxes[b];
+  const int local = ((int)blockIdx.x - B.blk_off) * kAtomBlock + (int)threadIdx.x;
+  if (local >= B.n_atoms) return;
+  const int64_t N = v.N;
+  const int32_t i = B.atom_off + local;
+  const int32_t c = v.cell[i];
+  const int32_t s0 = v.cell_start[c];
+  const int32_t n = v.cell_start[c + 1] - s0;
+  int rank = 0;
+  for (int k = 0; k < n; ++k) rank += v.tmp[s0 + k] < i;
+  if (rank >= n) rank = n - 1;   // only reachable if the lists were inconsistent
+  const int32_t dst = s0 + rank;
+  v.cell_atoms[dst] = i;
+  v.scell[dst] = c;
+  const double x = v.pos[i], y = v.pos[N + i], z = v.pos[2 * N + i];
+  const int kx = cell_coord(x, B.cinv[0], B.M[0]);
+  const int ky = cell_coord(y, B.cinv[1], B.M[1]);
+  const int kz = cell_coord(z, B.cinv[2], B.M[2]);
+  const double rx = x - ((double)kx + 0.5) * B.edge[0];
+  const double ry = y - ((double)ky + 0.5) * B.edge[1];
+  const double rz = z - ((double)kz + 0.5) * B.edge[2];
+  const int32_t tag = (i << 4) | ((int32_t)(v.type[i] & 1) << 3) | (kx & 7);
+  store_payload<PayT>(static_cast<PayT*>(v.payload), dst, rx, ry, rz, tag);
+}
+
+// ---- bonded terms ----
+template <typename P>
+struct V3 {
+  P x, y, z;
+};
+template <typename P>
+__device__ inline V3<P> v3(P x, P y, P z) {
+  return V3<P>{x, y, z};
+}
+template <typename P>
+__device__ inline P dot(V3<P> a, V3<P> b) {
+  return a.x * b.x + a.y * b.y + a.z * b.z;
+}
+template <typename P>
+__device__ inline V3<P> cross(V3<P> a, V3<P> b) {
+  return V3<P>{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+template <typename P>
+__device__ inline V3<P> scale(V3<P> a, P s) {
+  return V3<P>{a.x * s, a.y * s, a.z * s};
+}
+template <typename P>
+__device__ inline V3<P> add(V3<P> a, V3<P> b) {
+  return V3<P>{a.x + b.x, a.y + b.y, a.z + b.z};
+}
+template <typename P>
+__device__ inline V3<P> neg(V3<P> a) {
+  return V3<P>{-a.x, -a.y, -a.z};
+}
+
+__device__ inline double sqrt_p(double x) { return sqrt(x); }
+__device__ inline float sqrt_p(float x) { return sqrtf(x); }
+__device__ inline double atan2_p(double y, double x) { return atan2(y, x); }
+__device__ inline float atan2_p(float y, float x) { return atan2f(y, x); }
+
+// Minimum-image difference b - a along one dimension, in FP64, then cast.
+template <typename P>
+__device__ inline V3<P> mi_diff(const double* xs, int a, int b, int stride, const BoxDev& B) {
+  double d[3];
+  for (int k = 0; k < 3; ++k) {
+    double t = xs[k * stride + b] - xs[k * stride + a];
+    d[k] = t - B.L[k] * rint(t * B.invL[k]);
+  }
+  return v3<P>((P)d[0], (P)d[1], (P)d[2]);
+}
+
+template <typename P, bool KICK, bool ENERGY>
+__global__ __launch_bounds__(kAtomBlock) void k_bonded(Views v, FFDev ff, double dt) {
+  constexpr int S = kAtomBlock + 2 * kHalo;       // staged atoms: [g0 - 3, g0 + 256 + 3)
+  constexpr int T = kAtomBlock + kHalo;           // term starts:  [g0 - 3, g0 + 256)
+  __shared__ double xs[3 * S];
+  // per term start u: bond force on its first atom; angle forces on i and k;
+  // dihedral forces on i, j and l (the missing atom gets minus the sum)
+  __shared__ P fb[3 * T], fai[3 * T], fak[3 * T], fdi[3 * T], fdj[3 * T], fdl[3 * T];
+  __shared__ dd red[kAtomBlock / 64][5];
+
+  const int b = v.blk_box[blockIdx.x];
+  const BoxDev& B = v.boxes[b];
+  const int64_t N = v.N;
+  const int32_t g0 = B.atom_off + ((int)blockIdx.x - B.blk_off) * kAtomBlock;
+  const int32_t box_end = B.atom_off + B.n_atoms;
+  const int L = ff.chain_len;
+
+  for (int t = threadIdx.x; t < S; t += kAtomBlock) {
+    const int32_t g = g0 - kHalo + t;
+    const bool ok = g >= B.atom_off && g < box_end;
+    xs[t] = ok ? v.pos[g] : 0.0;
+    xs[S + t] = ok ? v.pos[N + g] : 0.0;
+    xs[2 * S + t] = ok ? v.pos[2 * N + g] : 0.0;
+  }
+  __syncthreads();
+
+  double e_b = 0.0, e_a = 0.0, e_d = 0.0, w_b = 0.0;
+  const P kb = (P)ff.kb, ka = (P)ff.ka, kphi = (P)ff.kphi;
+  for (int u = threadIdx.x; u < T; u += kAtomBlock) {
+    const int32_t p = g0 - kHalo + u;   // first atom of the terms starting here
+    const bool in_box = p >= B.atom_off && p < box_end;
+    const int q = in_box ? (int)((p - B.atom_off) % L) : L;   // site within the chain
+    const bool own = ENERGY && p >= g0 && p < g0 + kAtomBlock && in_box;
+    V3<P> zero = v3<P>(0, 0, 0);
+    // bond (p, p+1), Eq. (4)
+    V3<P> f_b = zero;
+    if (q + 1 < L) {
+      const V3<P> d = mi_diff<P>(xs, u, u + 1, S, B);      // x_{p+1} - x_p
+      const double d2 = (double)dot(d, d);
+      const double r = sqrt(d2);
+      const P dr = (P)(r - ff.b0);
+      f_b = scale(d, kb * dr / (P)r);                        // force on p
+      if (own) {
+        e_b += 0.5 * ff.kb * (double)dr * (double)dr;
+        w_b += (double)dot(d, neg(f_b));                     // (x_{p+1} - x_p) . F_{p+1}
+      }
+    }
+    // angle (p, p+1, p+2) at p+1, Eq. (5)
+    V3<P> f_ai = zero, f_ak = zero;
+    if (q + 2 < L) {
+      const V3<P> a = mi_diff<P>(xs, u + 1, u, S, B);      // x_i - x_j
+      const V3<P> c = mi_diff<P>(xs, u + 1, u + 2, S, B);  // x_k - x_j
+      const P ac = dot(a, c), aa = dot(a, a), cc = dot(c, c);
+      const V3<P> axc = cross(a, c);
+      const P s = sqrt_p(dot(axc, axc));                     // |a||c| sin(theta)
+      const P th = atan2_p(s, ac);
+      const P dth = (P)((double)th - ff.theta0);
+      const P g = ka * dth / s;
+      f_ai = scale(add(c, scale(a, -ac / aa)), g);
+      f_ak = scale(add(a, scale(c, -ac / cc)), g);
+      if (own) {
+        e_a += 0.5 * ff.ka * (double)dth * (double)dth;
+        w_b += (double)(dot(a, f_ai) + dot(c, f_ak));
+      }
+    }
+    // dihedral (p, p+1, p+2, p+3), Eq. (6), IUPAC angle
+    V3<P> f_di = zero, f_dj = zero, f_dl = zero;
+    if (q + 3 < L) {
+      const V3<P> rij = mi_diff<P>(xs, u + 1, u, S, B);      // x_i - x_j
+      const V3<P> rkj = mi_diff<P>(xs, u + 1, u + 2, S, B);  // x_k - x_j
+      const V3<P> rkl = mi_diff<P>(xs, u + 3, u + 2, S, B);  // x_k - x_l
+      const V3<P> m = cross(rij, rkj);
+      const V3<P> n = cross(rkj, rkl);
+      const P mm = dot(m, m), nn = dot(n, n), kk = dot(rkj, rkj);
+      const P lk = sqrt_p(kk);
+      const P craw = dot(m, n);
+      const P sraw = lk * dot(rij, n);
+      const P rho = sqrt_p(craw * craw + sraw * sraw);      // |m||n|
+      const P cphi = craw / rho, sphi = sraw / rho;
+      // cos(n phi), sin(n phi) by the angle-addition recurrence
+      P cn = cphi, sn = sphi;
+      for (int t = 1; t < ff.n_dih; ++t) {
+        const P c2 = cn * cphi - sn * sphi;
+        sn = sn * cphi + cn * sphi;
+        cn = c2;
+      }
+      const P cps = (P)ff.cos_phis, sps = (P)ff.sin_phis;
+      // E = kphi (1 + cos(n phi - phis)); dE/dphi = -n kphi sin(n phi - phis)
+      const P dEdphi = -(P)ff.n_dih * kphi * (sn * cps - cn * sps);
+      const V3<P> dpi = scale(m, lk / mm);                   // d phi / d x_i
+      const V3<P> dpl = scale(n, -lk / nn);                  // d phi / d x_l
+      const P pp = dot(rij, rkj) / kk, qq = dot(rkl, rkj) / kk;
+      const V3<P> dpj = add(scale(dpi, pp - (P)1), scale(dpl, -qq));
+      f_di = scale(dpi, -dEdphi);
+      f_dj = scale(dpj, -dEdphi);
+      f_dl = scale(dpl, -dEdphi);
+      if (own) {
+        e_d += (double)(kphi * ((P)1 + (cn * cps + sn * sps)));
+        // (x_i - x_j).F_i + (x_k - x_j).F_k + (x_l - x_j).F_l with F_k = -(F_i + F_j + F_l)
+        const V3<P> f_dk = neg(add(add(f_di, f_dj), f_dl));
+        const V3<P> rlj = add(rkj, neg(rkl));                // x_l - x_j
+        w_b += (double)(dot(rij, f_di) + dot(rkj, f_dk) + dot(rlj, f_dl));
+      }
+    }
+    fb[3 * u] = f_b.x; fb[3 * u + 1] = f_b.y; fb[3 * u + 2] = f_b.z;
+    fai[3 * u] = f_ai.x; fai[3 * u + 1] = f_ai.y; fai[3 * u + 2] = f_ai.z;
+    fak[3 * u] = f_ak.x; fak[3 * u + 1] = f_ak.y; fak[3 * u + 2] = f_ak.z;
+    fdi[3 * u] = f_di.x; fdi[3 * u + 1] = f_di.y; fdi[3 * u + 2] = f_di.z;
+    fdj[3 * u] = f_dj.x; fdj[3 * u + 1] = f_dj.y; fdj[3 * u + 2] = f_dj.z;
+    fdl[3 * u] = f_dl.x; fdl[3 * u + 1] = f_dl.y; fdl[3 * u + 2] = f_dl.z;
+  }
+  __syncthreads();
+
+  const int t = threadIdx.x;
+  const int32_t g = g0 + t;
+  double ke = 0.0;
+  if (g < box_end) {
+    const int u = t + kHalo;   // term start index of the terms that begin at atom g
+    P f[3];
+    for (int k = 0; k < 3; ++k) {
+      // fixed order: dihedrals (g as l, k, j, i), angles (k, j, i), bonds (second, first)
+      P s = fdl[3 * (u - 3) + k];
+      s += -(fdi[3 * (u - 2) + k] + fdj[3 * (u - 2) + k] + fdl[3 * (u - 2) + k]);
+      s += fdj[3 * (u - 1) + k];
+      s += fdi[3 * u + k];
+      s += fak[3 * (u - 2) + k];
+      s += -(fai[3 * (u - 1) + k] + fak[3 * (u - 1) + k]);
+      s += fai[3 * u + k];
+      s += -fb[3 * (u - 1) + k];
+      s += fb[3 * u + k];
+      f[k] = s;
+    }
+    const P* flj = static_cast<const P*>(v.f_lj);
+    P* ftot = static_cast<P*>(v.f_tot);
+    for (int k = 0; k < 3; ++k) {
+      f[k] += flj[k * N + g];
+      ftot[k * N + g] = f[k];
+    }
+    if (KICK || ENERGY) {
+      const int ty = v.type[g];
+      double vv[3];
+      for (int k = 0; k < 3; ++k) vv[k] = v.vel[k * N + g];
+      if (KICK) {
+        const double h = 0.5 * dt * ff.acc_over_m[ty];
+        for (int k = 0; k < 3; ++k) {
+          vv[k] += h * (double)f[k];
+          v.vel[k * N + g] = vv[k];
+        }
+      }
+      ke = ff.half_m_over_acc[ty] * (vv[0] * vv[0] + vv[1] * vv[1] + vv[2] * vv[2]);
+    }
+  }
+  if (KICK || ENERGY) {
+    // block partials: E_b, E_a, E_d, W_b, KE (double-double, fixed reduction order)
+    dd q[5] = {dd_from(e_b), dd_from(e_a), dd_from(e_d), dd_from(w_b), dd_from(ke)};
+    for (int k = 0; k < 5; ++k)
+      for (int off = 32; off > 0; off >>= 1) {
+        dd o{__shfl_xor(q[k].hi, off), __shfl_xor(q[k].lo, off)};
+        q[k] = dd_add(q[k], o);
+      }
+    if (lane() == 0)
+      for (int k = 0; k < 5; ++k) red[threadIdx.x >> 6][k] = q[k];
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int k = 0; k < 5; ++k) {
+        dd s = red[0][k];
+        for (int w = 1; w < kAtomBlock / 64; ++w) s = dd_add(s, red[w][k]);
+        v.part_bd[(int64_t)blockIdx.x * 5 + k] = s;
+      }
+  }
+}
+
+// One block per box: sum the block partials of the box in a fixed order.
+__device__ dd block_sum(const dd* part, int stride, int k, int first, int count, dd* sh) {
+  dd s{0.0, 0.0};
+  for (int t = threadIdx.x; t < count; t += blockDim.x) s = dd_add(s, part[(int64_t)(first + t) * stride + k]);
+  for (int off = 32; off > 0; off >>= 1) {
+    dd o{__shfl_xor(s.hi, off), __shfl_xor(s.lo, off)};
+    s = dd_add(s, o);
+  }
+  if (lane() == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  dd r = sh[0];
+  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = dd_add(r, sh[w]);
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(256) void k_reduce(Views v, int energy, int thermostat, double dt, double tau) {
+  __shared__ dd sh[4];
+  const int b = blockIdx.x;
+  const BoxDev& B = v.boxes[b];
+  const int first = B.blk_off;
+  const int count = (B.n_atoms + kAtomBlock - 1) / kAtomBlock;
+  const dd ke = block_sum(v.part_bd, 5, 4, first, count, sh);
+  const double KE = ke.hi + ke.lo;
+  const double T = 2.0 * KE / (B.dof * kRgas);
+  double* out = v.energy + (int64_t)b * 8;
+  if (energy) {
+    const int lfirst = B.lj_blk_off;
+    const int lcount = (b + 1 < v.n_boxes ? v.boxes[b + 1].lj_blk_off : v.n_lj_blocks) - lfirst;
+    dd q[7];
+    q[0] = block_sum(v.part_lj, 3, 0, lfirst, lcount, sh);
+    q[1] = block_sum(v.part_lj, 3, 1, lfirst, lcount, sh);
+    q[2] = block_sum(v.part_bd, 5, 0, first, count, sh);
+    q[3] = block_sum(v.part_bd, 5, 1, first, count, sh);
+    q[4] = block_sum(v.part_bd, 5, 2, first, count, sh);
+    q[5] = block_sum(v.part_lj, 3, 2, lfirst, lcount, sh);
+    q[6] = block_sum(v.part_bd, 5, 3, first, count, sh);
+    if (threadIdx.x == 0) {
+      out[0] = q[0].hi + q[0].lo;
+      out[1] = q[1].hi + q[1].lo;
+      out[2] = q[2].hi + q[2].lo;
+      out[3] = q[3].hi + q[3].lo;
+      out[4] = q[4].hi + q[4].lo;
+      const dd w = dd_add(q[5], q[6]);
+      out[7] = w.hi + w.lo;
+    }
+  }
+  if (threadIdx.x == 0) {
+    out[5] = KE;
+    out[6] = T;
+    if (thermostat) {
+      double lam = 1.0;
+      if (B.T0 > 0.0 && T > 0.0) lam = sqrt(1.0 + dt / tau * (B.T0 / T - 1.0));
+      v.lambda[b] = lam;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kAtomBlock) void k_finalize(Views v) {
+  const int b = v.blk_box[blockIdx.x];
+  const BoxDev& B = v.boxes[b];
+  const int local = ((int)blockIdx.x - B.blk_off) * kAtomBlock + (int)threadIdx.x;
+  if (local >= B.n_atoms) return;
+  const int64_t N = v.N;
+  const int64_t i = (int64_t)B.atom_off + local;
+  const double lam = v.lambda[b];
+  v.vel[i] *= lam;
+  v.vel[N + i] *= lam;
+  v.vel[2 * N + i] *= lam;
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t val) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = val;
+}
+__global__ void k_fill_f64(double* p, int64_t n, double val) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = val;
+}
+
+int grid_for(int64_t n, int block) {
+  int64_t g = (n + block - 1) / block;
+  if (g > 65535 * 8) g = 65535 * 8;
+  return (int)(g < 1 ? 1 : g);
+}
+
+}  // namespace
+
+void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, v);
+}
+void launch_fill_f64(double* p, int64_t n, double v, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, v);
+}
+
+void launch_bin_count(const Views& v, bool kick, double dt, const FFDev& ff, bool fp32_force,
+                      hipStream_t s) {
+  dim3 g(v.n_atom_blocks), blk(kAtomBlock);
+  if (!kick)
+    hipLaunchKernelGGL((k_bin_count<float, false>), g, blk, 0, s, v, (const float*)nullptr, dt, ff);
+  else if (fp32_force)
+    hipLaunchKernelGGL((k_bin_count<float, true>), g, blk, 0, s, v, (const float*)v.f_tot, dt, ff);
+  else
+    hipLaunchKernelGGL((k_bin_count<double, true>), g, blk, 0, s, v, (const double*)v.f_tot, dt, ff);
+}
+
+void launch_scan(const Views& v, hipStream_t s) {
+  const int n_tiles = (int)((v.C + kScanTile - 1) / kScanTile);
+  hipLaunchKernelGGL(k_scan_tiles, dim3(n_tiles), dim3(kScanBlock), 0, s, v.cnt, v.C, v.scan_tiles);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlock), 0, s, v.scan_tiles, n_tiles, v.cell_start, v.C);
+  hipLaunchKernelGGL(k_scan_apply, dim3(n_tiles), dim3(kScanBlock), 0, s, v.cnt, v.C, v.scan_tiles,
+                     v.cell_start);
+}
+
+void launch_scatter(const Views& v, hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter, dim3(v.n_atom_blocks), dim3(kAtomBlock), 0, s, v);
+}
+
+void launch_rank_payload(const Views& v, bool fp32, hipStream_t s) {
+  if (fp32)
+    hipLaunchKernelGGL(k_rank_payload<float4>, dim3(v.n_atom_blocks), dim3(kAtomBlock), 0, s, v);
+  else
+    hipLaunchKernelGGL(k_rank_payload<Pay64>, dim3(v.n_atom_blocks), dim3(kAtomBlock), 0, s, v);
+}
+
+void launch_bonded(const Views& v, const FFDev& ff, bool fp32, bool kick, bool energy, double dt,
+                   hipStream_t s) {
+  dim3 g(v.n_atom_blocks), b(kAtomBlock);
+#define MDK_BONDED(P, K, E) hipLaunchKernelGGL((k_bonded<P, K, E>), g, b, 0, s, v, ff, dt)
+  if (fp32) {
+    if (kick) { if (energy) MDK_BONDED(float, true, true); else MDK_BONDED(float, true, false); }
+    else { if (energy) MDK_BONDED(float, false, true); else MDK_BONDED(float, false, false); }
+  } else {
+    if (kick) { if (energy) MDK_BONDED(double, true, true); else MDK_BONDED(double, true, false); }
+    else { if (energy) MDK_BONDED(double, false, true); else MDK_BONDED(double, false, false); }
+  }
+#undef MDK_BONDED
+}
+
+void launch_reduce(const Views& v, bool energy, bool thermostat, double dt, double tau, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce, dim3(v.n_boxes), dim3(256), 0, s, v, energy ? 1 : 0, thermostat ? 1 : 0,
+                     dt, tau);
+}
+
+void launch_finalize(const Views& v, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(v.n_atom_blocks), dim3(kAtomBlock), 0, s, v);
+  launch_fill_f64(v.lambda, v.n_boxes, 1.0, s);
+}
+
+}  // namespace mdk

@@ -1,0 +1,296 @@
+"""ctypes binding of the C ABI declared in ``include/md.h`` (argument marshalling only).
+
+PyTorch supplies device memory and the HIP stream; every step of the simulation runs in
+the library's HIP kernels.  If ``libmd_gfx950.so`` is missing this module raises: there
+is no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmd_gfx950.so")
+
+MD_OK, MD_ERR_ARG, MD_ERR_BOX_TOO_SMALL, MD_ERR_NONFINITE = 0, -1, -2, -3
+MD_ERR_WORKSPACE, MD_ERR_HIP, MD_ERR_STATE = -4, -6, -7
+MD_PREC_FP64, MD_PREC_MIXED = 0, 1
+MD_LJ_AUTO, MD_LJ_ATOM, MD_LJ_CELLTILE = 0, 1, 2
+
+_D, _I32, _I64, _P = ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+
+
+class md_forcefield(ctypes.Structure):
+    _fields_ = [("mass", _D * 2), ("sigma", _D * 2), ("epsilon", _D * 2), ("kb", _D), ("b0", _D),
+                ("ka", _D), ("theta0_deg", _D), ("kphi", _D), ("phis_deg", _D), ("n_dih", _I32),
+                ("rc", _D), ("excl_depth", _I32)]
+
+
+class md_config(ctypes.Structure):
+    _fields_ = [("n_boxes", _I32), ("chain_len", _I32), ("n_chains", ctypes.POINTER(_I32)),
+                ("box", ctypes.POINTER(_D)), ("T0", ctypes.POINTER(_D)), ("dt_fs", _D), ("tau_fs", _D),
+                ("precision", _I32), ("cell_div", _I32), ("lj_kernel", _I32), ("use_graph", _I32)]
+
+
+class md_energy(ctypes.Structure):
+    _fields_ = [("e_lj", _D), ("e_lj_shifted", _D), ("e_bond", _D), ("e_angle", _D), ("e_dih", _D),
+                ("e_kin", _D), ("temperature", _D), ("virial", _D), ("step", _I64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class MDError(RuntimeError):
+    def __init__(self, status, what, detail=""):
+        self.status = status
+        super().__init__("%s failed: %s (%d)%s" % (what, _status_string(status), status,
+                                                    (": " + detail) if detail else ""))
+
+
+_LIB = None
+
+
+def load():
+    """Load the HIP library (raises if it has not been built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libmd_gfx950.so not found at %s; build it with __graft_entry__.build()" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    S = ctypes.c_int
+    sig = {
+        "md_workspace_bytes": (S, [_P, _P, ctypes.POINTER(ctypes.c_size_t)]),
+        "md_init_system": (S, [_P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)]),
+        "md_rebuild_bins": (S, [_P]),
+        "md_compute_forces": (S, [_P, _I32]),
+        "md_step": (S, [_P, _I32]),
+        "md_energies": (S, [_P, _P]),
+        "md_step_timed": (S, [_P, _I32, _P]),
+        "md_bins": (S, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_I64)]),
+        "md_grid": (S, [_P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
+        "md_forces": (S, [_P, ctypes.POINTER(_P), ctypes.POINTER(_I32)]),
+        "md_forces_lj": (S, [_P, ctypes.POINTER(_P), ctypes.POINTER(_I32)]),
+        "md_tuning": (S, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+        "md_destroy": (S, [_P]),
+        "md_status_string": (ctypes.c_char_p, [S]),
+        "md_last_error": (ctypes.c_char_p, [_P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _LIB = lib
+    return lib
+
+
+def _status_string(s):
+    try:
+        return load().md_status_string(s).decode()
+    except Exception:
+        return "status"
+
+
+def _check(status, what, ctx=None):
+    if status != MD_OK:
+        detail = ""
+        if ctx:
+            detail = load().md_last_error(ctx).decode(errors="replace")
+        raise MDError(status, what, detail)
+
+
+def make_forcefield(ff: dict) -> md_forcefield:
+    s = md_forcefield()
+    s.mass[:] = ff["mass"]
+    s.sigma[:] = ff["sigma"]
+    s.epsilon[:] = ff["epsilon"]
+    for k in ("kb", "b0", "ka", "theta0_deg", "kphi", "phis_deg", "rc"):
+        setattr(s, k, float(ff[k]))
+    s.n_dih = int(ff["n_dih"])
+    s.excl_depth = int(ff["excl_depth"])
+    return s
+
+
+class _Config:
+    """md_config plus the host arrays it points to (kept alive together)."""
+
+    def __init__(self, n_chains, boxes, T0, chain_len, dt, tau, precision, cell_div, lj_kernel, use_graph):
+        self.n_chains = np.ascontiguousarray(n_chains, dtype=np.int32)
+        self.box = np.ascontiguousarray(np.asarray(boxes, dtype=np.float64).reshape(-1, 3))
+        self.T0 = np.ascontiguousarray(T0, dtype=np.float64)
+        c = md_config()
+        c.n_boxes = self.n_chains.size
+        c.chain_len = int(chain_len)
+        c.n_chains = self.n_chains.ctypes.data_as(ctypes.POINTER(_I32))
+        c.box = self.box.ctypes.data_as(ctypes.POINTER(_D))
+        c.T0 = self.T0.ctypes.data_as(ctypes.POINTER(_D))
+        c.dt_fs = float(dt)
+        c.tau_fs = float(tau)
+        c.precision = MD_PREC_MIXED if precision in ("mixed", MD_PREC_MIXED) else MD_PREC_FP64
+        c.cell_div = int(cell_div)
+        c.lj_kernel = int(lj_kernel)
+        c.use_graph = int(bool(use_graph))
+        self.c = c
+
+
+def md_workspace_bytes(ff: md_forcefield, cfg: md_config) -> int:
+    n = ctypes.c_size_t()
+    _check(load().md_workspace_bytes(ctypes.byref(ff), ctypes.byref(cfg), ctypes.byref(n)), "md_workspace_bytes")
+    return n.value
+
+
+def md_init_system(ff, cfg, pos, vel, types, workspace, stream):
+    ctx = _P()
+    _check(load().md_init_system(ctypes.byref(ff), ctypes.byref(cfg), pos.data_ptr(), vel.data_ptr(),
+                                 types.data_ptr(), workspace.data_ptr(), workspace.numel(), stream,
+                                 ctypes.byref(ctx)), "md_init_system")
+    return ctx
+
+
+def md_rebuild_bins(ctx):
+    _check(load().md_rebuild_bins(ctx), "md_rebuild_bins", ctx)
+
+
+def md_compute_forces(ctx, with_energy=True):
+    _check(load().md_compute_forces(ctx, int(bool(with_energy))), "md_compute_forces", ctx)
+
+
+def md_step(ctx, n_steps):
+    _check(load().md_step(ctx, int(n_steps)), "md_step", ctx)
+
+
+MD_N_PHASES = 7
+PHASES = ("integrate_bin", "scan", "scatter", "rank_payload", "lj", "bonded_kick", "reduce")
+
+
+def md_step_timed(ctx, n_steps):
+    ms = (_D * MD_N_PHASES)()
+    _check(load().md_step_timed(ctx, int(n_steps), ms), "md_step_timed", ctx)
+    return dict(zip(PHASES, ms[:]))
+
+
+def md_energies(ctx, n_boxes):
+    out = (md_energy * n_boxes)()
+    _check(load().md_energies(ctx, out), "md_energies", ctx)
+    return [e.as_dict() for e in out]
+
+
+def md_bins(ctx):
+    cs, ca, n = _P(), _P(), _I64()
+    _check(load().md_bins(ctx, ctypes.byref(cs), ctypes.byref(ca), ctypes.byref(n)), "md_bins", ctx)
+    return cs.value, ca.value, n.value
+
+
+def md_grid(ctx, box):
+    M = (_I32 * 3)()
+    co, ao = _I64(), _I64()
+    _check(load().md_grid(ctx, int(box), M, ctypes.byref(co), ctypes.byref(ao)), "md_grid", ctx)
+    return np.array(M[:], dtype=np.int32), co.value, ao.value
+
+
+def md_forces(ctx):
+    f, fp32 = _P(), _I32()
+    _check(load().md_forces(ctx, ctypes.byref(f), ctypes.byref(fp32)), "md_forces", ctx)
+    return f.value, bool(fp32.value)
+
+
+def md_forces_lj(ctx):
+    f, fp32 = _P(), _I32()
+    _check(load().md_forces_lj(ctx, ctypes.byref(f), ctypes.byref(fp32)), "md_forces_lj", ctx)
+    return f.value, bool(fp32.value)
+
+
+def md_tuning(ctx):
+    r, k = _I32(), _I32()
+    _check(load().md_tuning(ctx, ctypes.byref(r), ctypes.byref(k)), "md_tuning", ctx)
+    return r.value, k.value
+
+
+def md_destroy(ctx):
+    _check(load().md_destroy(ctx), "md_destroy")
+
+
+class MDSystem:
+    """One or more periodic boxes on one GPU: torch owns the device buffers, the HIP
+    library owns every computation on them."""
+
+    def __init__(self, ff: dict, n_chains, boxes, T0, pos, vel, types, chain_len=300, dt=1.0, tau=100.0,
+                 precision="mixed", cell_div=1, lj_kernel=MD_LJ_ATOM, use_graph=False, device="cuda:0"):
+        load()
+        self.device = torch.device(device)
+        self.ff = make_forcefield(ff)
+        self.cfg = _Config(n_chains, boxes, T0, chain_len, dt, tau, precision, cell_div, lj_kernel, use_graph)
+        self.n_boxes = self.cfg.c.n_boxes
+        pos = np.ascontiguousarray(pos, dtype=np.float64)
+        vel = np.ascontiguousarray(vel, dtype=np.float64)
+        self.N = pos.shape[1]
+        assert pos.shape == (3, self.N) and vel.shape == (3, self.N)
+        assert self.N == int(self.cfg.n_chains.sum()) * chain_len
+        self.pos = torch.from_numpy(pos).to(self.device).contiguous()
+        self.vel = torch.from_numpy(vel).to(self.device).contiguous()
+        self.types = torch.from_numpy(np.ascontiguousarray(types, dtype=np.uint8)).to(self.device)
+        nbytes = md_workspace_bytes(self.ff, self.cfg.c)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.ctx = md_init_system(self.ff, self.cfg.c, self.pos, self.vel, self.types, self.workspace,
+                                  self.stream.cuda_stream)
+
+    # --- the C ABI, one call each ---
+    def rebuild_bins(self):
+        md_rebuild_bins(self.ctx)
+
+    def compute_forces(self, with_energy=True):
+        md_compute_forces(self.ctx, with_energy)
+
+    def step(self, n):
+        md_step(self.ctx, n)
+
+    def step_timed(self, n):
+        return md_step_timed(self.ctx, n)
+
+    def energies(self):
+        return md_energies(self.ctx, self.n_boxes)
+
+    def tuning(self):
+        return md_tuning(self.ctx)
+
+    def grid(self, box=0):
+        return md_grid(self.ctx, box)
+
+    # --- device views copied to host ---
+    def _ws_view(self, ptr, count, dtype):
+        off = ptr - self.workspace.data_ptr()
+        itemsize = torch.empty(0, dtype=dtype).element_size()
+        assert 0 <= off and off + count * itemsize <= self.workspace.numel()
+        return self.workspace[off:off + count * itemsize].view(dtype)
+
+    def bins(self):
+        cs, ca, n_cells = md_bins(self.ctx)
+        torch.cuda.synchronize(self.device)
+        start = self._ws_view(cs, n_cells + 1, torch.int32).cpu().numpy()
+        atoms = self._ws_view(ca, self.N, torch.int32).cpu().numpy()
+        return start, atoms
+
+    def forces(self, lj_only=False):
+        ptr, fp32 = (md_forces_lj if lj_only else md_forces)(self.ctx)
+        torch.cuda.synchronize(self.device)
+        t = self._ws_view(ptr, 3 * self.N, torch.float32 if fp32 else torch.float64)
+        return t.cpu().numpy().astype(np.float64).reshape(3, self.N)
+
+    def state(self):
+        torch.cuda.synchronize(self.device)
+        return self.pos.cpu().numpy().copy(), self.vel.cpu().numpy().copy()
+
+    def close(self):
+        if self.ctx:
+            md_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

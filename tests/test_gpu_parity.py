@@ -1,0 +1,155 @@
+"""GPU parity against the FP64 oracle, through the C ABI (gfx950)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from pe_melt import make_melt
+
+pytestmark = pytest.mark.gpu
+
+# Force error metric: max_i |F_gpu,i - F_ora,i| / F_rms(ora), F_rms = sqrt(mean_i |F_ora,i|^2)
+TOL_MIXED = 1e-5     # FP32 forces
+TOL_FP64 = 1e-10     # FP64 forces (summation order and cell-relative differences differ)
+
+
+def norm_err(f, ref):
+    frms = np.sqrt(np.mean(np.sum(ref ** 2, axis=0)))
+    return float(np.max(np.sqrt(np.sum((f - ref) ** 2, axis=0))) / frms)
+
+
+def make_system(m, ff, precision, R=1, T0=0.0, **kw):
+    from paper_1001_3764_amd.md import MDSystem
+    print("system: N=%d precision=%s R=%d T0=%g %s" % (m.n_atoms, precision, R, T0, kw), flush=True)
+    return MDSystem(ff, [m.n_chains], m.box[None, :], [T0], m.pos, m.vel, m.types,
+                    chain_len=m.chain_len, precision=precision, cell_div=R, **kw)
+
+
+@pytest.fixture(scope="module")
+def melt():
+    return make_melt(10, density=0.80, T=500.0, seed_melt=1000, seed_vel=1001, jitter=0.05)
+
+
+@pytest.mark.parametrize("R", [1, 2])
+def test_bins_bit_exact(ff, melt, R):
+    s = make_system(melt, ff, "mixed", R)
+    start, atoms = s.bins()
+    M, co, ao = s.grid(0)
+    assert co == 0 and ao == 0
+    assert np.all(M == np.floor(melt.box * R / ff["rc"]))
+    cell = O.cell_index(melt.pos, melt.box, M)
+    cnt, ostart, oatoms = O.bin_atoms(cell, int(np.prod(M)))
+    np.testing.assert_array_equal(start, ostart)
+    np.testing.assert_array_equal(atoms, oatoms)
+    s.close()
+
+
+def test_wrap_and_bins_bit_exact_from_outside_the_box(ff, melt):
+    """Positions shifted by whole and fractional box lengths: the GPU wrap and cell index
+    must equal the oracle's bit for bit."""
+    rng = np.random.default_rng(12)
+    p = melt.pos + melt.box[:, None] * rng.integers(-2, 3, size=melt.pos.shape)
+    p[:, :50] += 1e-13          # a few just past the faces
+    from paper_1001_3764_amd.md import MDSystem
+    s = MDSystem(ff, [melt.n_chains], melt.box[None, :], [0.0], p, melt.vel, melt.types,
+                 precision="fp64", cell_div=1)
+    pos, _ = s.state()
+    np.testing.assert_array_equal(pos, O.wrap(p, melt.box))
+    start, atoms = s.bins()
+    M, _, _ = s.grid(0)
+    cnt, ostart, oatoms = O.bin_atoms(O.cell_index(O.wrap(p, melt.box), melt.box, M), int(np.prod(M)))
+    np.testing.assert_array_equal(start, ostart)
+    np.testing.assert_array_equal(atoms, oatoms)
+    s.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", TOL_FP64), ("mixed", TOL_MIXED)])
+@pytest.mark.parametrize("R", [1, 2])
+def test_forces_and_energies(ff, melt, precision, tol, R):
+    s = make_system(melt, ff, precision, R)
+    f = s.forces()
+    flj = s.forces(lj_only=True)
+    e = s.energies()[0]
+    fo_lj, eo = O.lj_cells(ff, melt.pos, melt.types, melt.box, 300)
+    fo_b, eb = O.bonded(ff, melt.pos, melt.box, 300)
+    err_lj = norm_err(flj, fo_lj)
+    err_b = norm_err(f - flj, fo_b)
+    err = norm_err(f, fo_lj + fo_b)
+    print("force error %s R=%d: LJ %.3e bonded %.3e total %.3e" % (precision, R, err_lj, err_b, err))
+    assert err_lj <= tol and err_b <= tol and err <= tol
+    # energies: compensated FP64 sums of per-pair/per-term values
+    etol = 1e-12 if precision == "fp64" else 2e-6
+    assert e["e_lj"] == pytest.approx(eo["e_lj"], rel=etol)
+    assert e["e_lj_shifted"] == pytest.approx(eo["e_lj_shifted"], rel=etol)
+    assert e["e_bond"] == pytest.approx(eb["e_bond"], rel=etol)
+    assert e["e_angle"] == pytest.approx(eb["e_angle"], rel=etol)
+    assert e["e_dih"] == pytest.approx(eb["e_dih"], rel=etol)
+    assert e["virial"] == pytest.approx(eo["virial_lj"] + eb["virial_bonded"], rel=max(etol, 1e-11))
+    ke, T = O.kinetic(ff, melt.vel, melt.types)
+    assert e["e_kin"] == pytest.approx(ke, rel=1e-13)
+    assert e["temperature"] == pytest.approx(T, rel=1e-13)
+    # Newton's third law on the GPU forces
+    assert np.abs(f.sum(axis=1)).max() <= (1e-9 if precision == "fp64" else 1e-4) * np.abs(f).sum() / f.shape[1]
+    s.close()
+
+
+@pytest.mark.parametrize("precision,xtol", [("fp64", 1e-9), ("mixed", 1e-4)])
+def test_trajectory_100_steps(ff, melt, precision, xtol):
+    """The 3,000-atom melt, NVE, 100 steps of 1 fs: positions against the oracle."""
+    s = make_system(melt, ff, precision, 1)
+    f0, _ = O.forces(ff, melt.pos, melt.types, melt.box, 300)
+    worst = []
+    p_o, v_o, f_o = melt.pos, melt.vel, f0
+    for chunk in range(4):
+        s.step(25)
+        p_o, v_o, f_o, e_o = O.run(ff, p_o, v_o, f_o, melt.types, melt.box, 300, 25)
+        p, v = s.state()
+        d = p - p_o
+        d -= melt.box[:, None] * np.round(d / melt.box[:, None])
+        worst.append(float(np.abs(d).max()))
+    e = s.energies()[0]
+    print("trajectory %s max|dx| per 25 steps: %s" % (precision, worst))
+    assert worst[-1] <= xtol
+    assert e["step"] == 100
+    etol = 1e-9 if precision == "fp64" else 1e-4
+    assert e["e_kin"] == pytest.approx(e_o["e_kin"], rel=etol)
+    assert e["e_lj"] == pytest.approx(e_o["e_lj"], rel=etol * 10)
+    s.close()
+
+
+def test_berendsen_quench_matches_oracle(ff, melt):
+    s = make_system(melt, ff, "fp64", 1, T0=300.0)
+    f0, _ = O.forces(ff, melt.pos, melt.types, melt.box, 300)
+    s.step(20)
+    p_o, v_o, f_o, e_o = O.run(ff, melt.pos, melt.vel, f0, melt.types, melt.box, 300, 20, T0=300.0)
+    e = s.energies()[0]
+    assert e["temperature"] == pytest.approx(e_o["temperature"], rel=1e-10)
+    p, v = s.state()
+    assert np.abs(v - v_o).max() < 1e-10
+    s.close()
+
+
+def test_graph_replay_is_bit_identical(ff, melt):
+    a = make_system(melt, ff, "mixed", 1, T0=400.0, use_graph=False)
+    b = make_system(melt, ff, "mixed", 1, T0=400.0, use_graph=True)
+    for _ in range(3):
+        a.step(7)
+        b.step(7)
+        pa, va = a.state()
+        pb, vb = b.state()
+        assert np.array_equal(pa, pb) and np.array_equal(va, vb)
+    assert a.energies()[0] == b.energies()[0]
+    a.close()
+    b.close()
+
+
+def test_timed_step_matches_plain_step(ff, melt):
+    a = make_system(melt, ff, "mixed", 1)
+    b = make_system(melt, ff, "mixed", 1)
+    a.step(5)
+    ms = b.step_timed(5)
+    assert set(ms) >= {"lj", "bonded_kick", "integrate_bin"} and all(v >= 0 for v in ms.values())
+    pa, va = a.state()
+    pb, vb = b.state()
+    assert np.array_equal(pa, pb) and np.array_equal(va, vb)
+    a.close()
+    b.close()
