@@ -64,8 +64,10 @@ typedef enum {
 typedef enum {
   MD_LJ_AUTO = 0,       /* chosen by the autotuner at init */
   MD_LJ_ATOM = 1,       /* one lane per home atom walking the neighbouring cells */
-  MD_LJ_CELLTILE = 2    /* one wavefront per home cell: home atoms wave-uniform, candidate
+  MD_LJ_CELLTILE = 2,   /* one wavefront per home cell: home atoms wave-uniform, candidate
                            atoms across the lanes */
+  MD_LJ_CELLTILE_NB = 3 /* as MD_LJ_CELLTILE, with the pair force evaluated on every lane and
+                           zeroed outside the cutoff instead of branching (mixed precision) */
 } md_lj_kernel;
 
 /* Force field (Table I, Eqs. 2-6).  Types: 0 = CH2 (C_32), 1 = CH3 (C_33).  LJ pair

@@ -81,7 +81,7 @@ md_status validate(const md_forcefield* ff, const md_config* cfg, std::string* w
   if (!finite_pos(cfg->dt_fs) || !finite_pos(cfg->tau_fs)) { *why = "dt and tau must be > 0"; return MD_ERR_ARG; }
   if (cfg->precision != MD_PREC_FP64 && cfg->precision != MD_PREC_MIXED) { *why = "bad precision"; return MD_ERR_ARG; }
   if (cfg->cell_div < 0 || cfg->cell_div > 3) { *why = "cell_div must be 0..3"; return MD_ERR_ARG; }
-  if (cfg->lj_kernel < 0 || cfg->lj_kernel > 2) { *why = "lj_kernel must be 0..2"; return MD_ERR_ARG; }
+  if (cfg->lj_kernel < 0 || cfg->lj_kernel > 3) { *why = "lj_kernel must be 0..3"; return MD_ERR_ARG; }
   int64_t N = 0;
   for (int b = 0; b < cfg->n_boxes; ++b) {
     if (cfg->n_chains[b] < 1) { *why = "every box needs at least one chain"; return MD_ERR_ARG; }
@@ -136,6 +136,7 @@ Plan make_plan(const md_forcefield* ff, const md_config* cfg, int R, int kernel)
       B.M[d] = M;
       B.cinv[d] = (double)M / L;
       B.edge[d] = L / (double)M;
+      B.edge_q[d] = (int32_t)std::lrint(B.edge[d] * kFix);
       nc *= M;
     }
     B.atom_off = (int32_t)atom;
@@ -339,8 +340,11 @@ md_status autotune(md_ctx* c, const md_config* cfg, int* bestR, int* bestK) {
     for (int R = 1; R <= 2; ++R)
       if (grid_ok(&c->ff, cfg, R)) Rs.push_back(R);
   if (cfg->lj_kernel) Ks.push_back(cfg->lj_kernel);
-  else
+  else {
     Ks.push_back(MD_LJ_ATOM);
+    Ks.push_back(MD_LJ_CELLTILE);
+    if (cfg->precision == MD_PREC_MIXED) Ks.push_back(MD_LJ_CELLTILE_NB);
+  }
   if (Rs.empty()) return fail(c, MD_ERR_BOX_TOO_SMALL, "no stencil fits every box");
   hipEvent_t e0, e1;
   md_status st;
@@ -352,6 +356,7 @@ md_status autotune(md_ctx* c, const md_config* cfg, int* bestR, int* bestK) {
   for (int R : Rs)
     for (int K : Ks) {
       if (Rs.size() * Ks.size() == 1) break;
+      if (K >= MD_LJ_CELLTILE && R > kTileMaxR) continue;
       if ((st = configure(c, cfg, R, K))) break;
       enqueue_rebuild(c, c->stream, false);
       enqueue_forces(c, c->stream, false, false);
@@ -390,8 +395,9 @@ md_status md_workspace_bytes(const md_forcefield* ff, const md_config* cfg, size
     if (cfg->cell_div && cfg->cell_div != R) continue;
     if (!cfg->cell_div && R > 2) continue;
     if (!grid_ok(ff, cfg, R)) continue;
-    for (int K = 1; K <= 2; ++K) {
+    for (int K = 1; K <= 3; ++K) {
       if (cfg->lj_kernel && cfg->lj_kernel != K) continue;
+      if (K >= MD_LJ_CELLTILE && R > kTileMaxR) continue;
       best = std::max(best, carve(make_plan(ff, cfg, R, K), nullptr, nullptr));
       any = true;
     }
@@ -413,7 +419,7 @@ md_status md_init_system(const md_forcefield* ff, const md_config* cfg, double* 
   if (((uintptr_t)workspace) % kAlign) return MD_ERR_WORKSPACE;
   if (cfg->cell_div && !grid_ok(ff, cfg, cfg->cell_div)) return MD_ERR_BOX_TOO_SMALL;
   if (!cfg->cell_div && !grid_ok(ff, cfg, 1)) return MD_ERR_BOX_TOO_SMALL;
-  if (cfg->lj_kernel == MD_LJ_CELLTILE) return MD_ERR_ARG;   // not available in this build
+  if (cfg->lj_kernel >= MD_LJ_CELLTILE && cfg->cell_div > kTileMaxR) return MD_ERR_ARG;
   size_t need = 0;
   if ((st = md_workspace_bytes(ff, cfg, &need))) return st;
   if (ws_bytes < need) return MD_ERR_WORKSPACE;

@@ -20,6 +20,14 @@ constexpr int kHalo = 3;          // a dihedral reaches 3 atoms beyond its first
 constexpr double kAccUnit = 4.184e-4;
 constexpr double kRgas = 1.987204259e-3;
 
+// Mixed-precision payload: coordinates relative to the cell centre as int32 fixed
+// point in units of 2^-25 A, so differences (and cell shifts) are exact integers and
+// are rounded once when converted to FP32.  Range: |value| < 64 A.
+constexpr int kFixBits = 25;
+constexpr double kFix = 33554432.0;               // 2^25
+constexpr float kInvFixF = 2.98023223876953125e-8f;   // 2^-25
+constexpr float kInvFix2F = 8.8817841970012523e-16f;  // 2^-50
+
 // tag of a sorted atom: global index << 4 | type << 3 | (cell x-index & 7)
 __host__ __device__ inline int32_t tag_index(int32_t tag) { return tag >> 4; }
 __host__ __device__ inline int32_t tag_type(int32_t tag) { return (tag >> 3) & 1; }
@@ -31,6 +39,7 @@ struct BoxDev {
   double cinv[3];         // M/L: cell index scale
   double edge[3];         // L/M
   int32_t M[3];
+  int32_t edge_q[3];      // cell edge in fixed-point units (rint(edge * 2^25))
   int32_t atom_off, n_atoms;
   int32_t cell_off, n_cells;
   int32_t blk_off;        // first per-atom block (kAtomBlock) of this box
@@ -84,7 +93,7 @@ struct Views {
   int32_t* tmp;        // [N] unordered cell lists
   int32_t* cell_atoms; // [N] ordered cell lists
   int32_t* scell;      // [N] cell of each sorted slot
-  void* payload;       // [N] float4 (mixed) / double4 (fp64), cell-centre-relative xyz + tag
+  void* payload;       // [N] int4 fixed point (mixed) / double4 (fp64): cell-centre-relative xyz + tag
   void* f_lj;          // [3N] LJ force, prec
   void* f_tot;         // [3N] total force, prec
   int32_t* scan_tiles; // [n_tiles]
@@ -114,5 +123,8 @@ void launch_finalize(const Views& v, hipStream_t s);
 // ---- launchers (md_lj.hip) ----
 void launch_lj(const Views& v, const FFDev& ff, bool fp32, int kernel, bool energy, hipStream_t s);
 int64_t lj_blocks_for_box(int kernel, int64_t n_atoms, int64_t n_cells);
+constexpr int kTileWaves = 4;     // home cells per block of the cell-tile kernel
+constexpr int kXcds = 8;          // accelerator complex dies of an MI355X (one L2 each)
+constexpr int kTileMaxR = 2;      // stencil radii the cell-tile kernel supports
 
 }  // namespace mdk

@@ -206,9 +206,9 @@ template <typename PayT>
 __device__ inline void store_payload(PayT* p, int64_t dst, double rx, double ry, double rz, int32_t tag);
 
 template <>
-__device__ inline void store_payload<float4>(float4* p, int64_t dst, double rx, double ry, double rz,
-                                             int32_t tag) {
-  p[dst] = make_float4((float)rx, (float)ry, (float)rz, __int_as_float(tag));
+__device__ inline void store_payload<int4>(int4* p, int64_t dst, double rx, double ry, double rz,
+                                           int32_t tag) {
+  p[dst] = make_int4((int)rint(rx * kFix), (int)rint(ry * kFix), (int)rint(rz * kFix), tag);
 }
 template <>
 __device__ inline void store_payload<Pay64>(Pay64* p, int64_t dst, double rx, double ry, double rz,
@@ -589,7 +589,7 @@ void launch_scatter(const Views& v, hipStream_t s) {
 
 void launch_rank_payload(const Views& v, bool fp32, hipStream_t s) {
   if (fp32)
-    hipLaunchKernelGGL(k_rank_payload<float4>, dim3(v.n_atom_blocks), dim3(kAtomBlock), 0, s, v);
+    hipLaunchKernelGGL(k_rank_payload<int4>, dim3(v.n_atom_blocks), dim3(kAtomBlock), 0, s, v);
   else
     hipLaunchKernelGGL(k_rank_payload<Pay64>, dim3(v.n_atom_blocks), dim3(kAtomBlock), 0, s, v);
 }

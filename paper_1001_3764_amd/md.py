@@ -13,12 +13,13 @@ import os
 import numpy as np
 import torch
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmd_gfx950.so")
+LIB_PATH = os.environ.get("PAPER_1001_3764_AMD_LIB") or os.path.join(
+    os.path.dirname(os.path.abspath(__file__)), "libmd_gfx950.so")
 
 MD_OK, MD_ERR_ARG, MD_ERR_BOX_TOO_SMALL, MD_ERR_NONFINITE = 0, -1, -2, -3
 MD_ERR_WORKSPACE, MD_ERR_HIP, MD_ERR_STATE = -4, -6, -7
 MD_PREC_FP64, MD_PREC_MIXED = 0, 1
-MD_LJ_AUTO, MD_LJ_ATOM, MD_LJ_CELLTILE = 0, 1, 2
+MD_LJ_AUTO, MD_LJ_ATOM, MD_LJ_CELLTILE, MD_LJ_CELLTILE_NB = 0, 1, 2, 3
 
 _D, _I32, _I64, _P = ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
 

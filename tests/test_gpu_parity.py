@@ -62,10 +62,11 @@ def test_wrap_and_bins_bit_exact_from_outside_the_box(ff, melt):
     s.close()
 
 
+@pytest.mark.parametrize("kernel", [1, 2, 3])
 @pytest.mark.parametrize("precision,tol", [("fp64", TOL_FP64), ("mixed", TOL_MIXED)])
 @pytest.mark.parametrize("R", [1, 2])
-def test_forces_and_energies(ff, melt, precision, tol, R):
-    s = make_system(melt, ff, precision, R)
+def test_forces_and_energies(ff, melt, precision, tol, R, kernel):
+    s = make_system(melt, ff, precision, R, lj_kernel=kernel)
     f = s.forces()
     flj = s.forces(lj_only=True)
     e = s.energies()[0]
@@ -74,7 +75,7 @@ def test_forces_and_energies(ff, melt, precision, tol, R):
     err_lj = norm_err(flj, fo_lj)
     err_b = norm_err(f - flj, fo_b)
     err = norm_err(f, fo_lj + fo_b)
-    print("force error %s R=%d: LJ %.3e bonded %.3e total %.3e" % (precision, R, err_lj, err_b, err))
+    print("force error %s R=%d kernel=%d: LJ %.3e bonded %.3e total %.3e" % (precision, R, kernel, err_lj, err_b, err))
     assert err_lj <= tol and err_b <= tol and err <= tol
     # energies: compensated FP64 sums of per-pair/per-term values
     etol = 1e-12 if precision == "fp64" else 2e-6
@@ -92,10 +93,11 @@ def test_forces_and_energies(ff, melt, precision, tol, R):
     s.close()
 
 
+@pytest.mark.parametrize("kernel", [1, 2])
 @pytest.mark.parametrize("precision,xtol", [("fp64", 1e-9), ("mixed", 1e-4)])
-def test_trajectory_100_steps(ff, melt, precision, xtol):
+def test_trajectory_100_steps(ff, melt, precision, xtol, kernel):
     """The 3,000-atom melt, NVE, 100 steps of 1 fs: positions against the oracle."""
-    s = make_system(melt, ff, precision, 1)
+    s = make_system(melt, ff, precision, 1, lj_kernel=kernel)
     f0, _ = O.forces(ff, melt.pos, melt.types, melt.box, 300)
     worst = []
     p_o, v_o, f_o = melt.pos, melt.vel, f0
@@ -153,3 +155,103 @@ def test_timed_step_matches_plain_step(ff, melt):
     assert np.array_equal(pa, pb) and np.array_equal(va, vb)
     a.close()
     b.close()
+
+
+def test_general_types_and_dihedral_phase(ff, melt):
+    """Unequal LJ types (Lorentz-Berthelot mixing) and a dihedral with n = 2, phi_s = 30 deg:
+    the general code paths of both kernels against the oracle."""
+    ffg = dict(ff, sigma=(3.47, 3.70), epsilon=(0.0951, 0.1200), n_dih=2, phis_deg=30.0)
+    fo_lj, eo = O.lj_cells(ffg, melt.pos, melt.types, melt.box, 300)
+    fo_b, eb = O.bonded(ffg, melt.pos, melt.box, 300)
+    for precision, tol in (("fp64", TOL_FP64), ("mixed", TOL_MIXED)):
+        for kernel in (1, 2):
+            s = make_system(melt, ffg, precision, 1, lj_kernel=kernel)
+            f = s.forces()
+            flj = s.forces(lj_only=True)
+            e = s.energies()[0]
+            assert norm_err(flj, fo_lj) <= tol
+            assert norm_err(f - flj, fo_b) <= tol
+            assert e["e_dih"] == pytest.approx(eb["e_dih"], rel=1e-12 if precision == "fp64" else 2e-6)
+            s.close()
+
+
+def _ensemble(n_boxes=3):
+    melts = [make_melt(c, density=0.80, T=300.0 + 50 * k, seed_melt=900 + k, seed_vel=950 + k, jitter=0.05)
+             for k, c in enumerate((4, 11, 7)[:n_boxes])]
+    return melts
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("kernel", [1, 2, 3])
+def test_batched_boxes(ff, precision, kernel):
+    """Three boxes of different sizes in one context: bins, forces and a 10-step run of each
+    box equal the box run alone (bit for bit) and match the oracle."""
+    from paper_1001_3764_amd.md import MDSystem
+    melts = _ensemble()
+    pos = np.concatenate([m.pos for m in melts], axis=1)
+    vel = np.concatenate([m.vel for m in melts], axis=1)
+    types = np.concatenate([m.types for m in melts])
+    T0 = [280.0, 0.0, 420.0]
+    s = MDSystem(ff, [m.n_chains for m in melts], np.stack([m.box for m in melts]), T0, pos, vel, types,
+                 precision=precision, cell_div=1, lj_kernel=kernel)
+    start, atoms = s.bins()
+    f_all = s.forces()
+    s.step(10)
+    p_all, v_all = s.state()
+    e_all = s.energies()
+    off = 0
+    for b, m in enumerate(melts):
+        n = m.n_atoms
+        M, co, ao = s.grid(b)
+        assert ao == off
+        nc = int(np.prod(M))
+        _, ostart, oatoms = O.bin_atoms(O.cell_index(m.pos, m.box, M), nc)
+        np.testing.assert_array_equal(start[co:co + nc + 1] - start[co], ostart)
+        np.testing.assert_array_equal(atoms[off:off + n] - off, oatoms)
+        fo, _ = O.forces(ff, m.pos, m.types, m.box, 300)
+        assert norm_err(f_all[:, off:off + n], fo) <= (TOL_FP64 if precision == "fp64" else TOL_MIXED)
+        alone = MDSystem(ff, [m.n_chains], m.box[None, :], [T0[b]], m.pos, m.vel, m.types,
+                         precision=precision, cell_div=1, lj_kernel=kernel)
+        alone.step(10)
+        p1, v1 = alone.state()
+        assert np.array_equal(p1, p_all[:, off:off + n]) and np.array_equal(v1, v_all[:, off:off + n])
+        e1 = alone.energies()[0]
+        assert e1["e_kin"] == e_all[b]["e_kin"] and e1["e_lj"] == e_all[b]["e_lj"]
+        alone.close()
+        off += n
+    s.close()
+
+
+def test_error_paths(ff, melt):
+    import paper_1001_3764_amd.md as md
+    # box below 2R+1 cells: refused on the host at init
+    small = make_melt(2, density=0.80, seed_melt=5)
+    with pytest.raises(md.MDError) as ei:
+        md.MDSystem(ff, [2], small.box[None, :], [0.0], small.pos, small.vel, small.types)
+    assert ei.value.status == md.MD_ERR_BOX_TOO_SMALL
+    # bad arguments
+    with pytest.raises(md.MDError) as ei:
+        md.MDSystem(dict(ff, rc=-1.0), [melt.n_chains], melt.box[None, :], [0.0], melt.pos, melt.vel,
+                    melt.types)
+    assert ei.value.status == md.MD_ERR_ARG
+    # a non-finite coordinate is flagged by the device and the context refuses to step
+    bad = melt.pos.copy()
+    bad[1, 17] = np.nan
+    s = md.MDSystem(ff, [melt.n_chains], melt.box[None, :], [0.0], bad, melt.vel, melt.types)
+    with pytest.raises(md.MDError) as ei:
+        s.energies()
+    assert ei.value.status == md.MD_ERR_NONFINITE
+    with pytest.raises(md.MDError) as ei:
+        s.step(1)
+    assert ei.value.status == md.MD_ERR_STATE
+    s.close()
+
+
+def test_runs_are_bitwise_reproducible(ff, melt):
+    runs = []
+    for _ in range(2):
+        s = make_system(melt, ff, "mixed", 2, T0=350.0, lj_kernel=2)
+        s.step(15)
+        runs.append(s.state())
+        s.close()
+    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
