@@ -120,6 +120,8 @@ void launch_reduce(const Views& v, bool energy, bool thermostat, double dt, doub
                    hipStream_t s);
 void launch_finalize(const Views& v, hipStream_t s);
 
+constexpr int kTileHomesMixed = 8;   // home atoms per pass of a mixed cell-tile wave
+
 // ---- launchers (md_lj.hip) ----
 void launch_lj(const Views& v, const FFDev& ff, bool fp32, int kernel, bool energy, hipStream_t s);
 int64_t lj_blocks_for_box(int kernel, int64_t n_atoms, int64_t n_cells);

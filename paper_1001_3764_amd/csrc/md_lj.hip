@@ -36,6 +36,17 @@ __device__ inline float rcp_f(float x) { return __builtin_amdgcn_rcpf(x); }
 
 __device__ inline int lane() { return (int)(threadIdx.x & 63); }
 
+// Number of set bits of a wave mask below this lane.
+__device__ inline int lanes_below(uint64_t m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Relative half-width of the band around rc^2 decided in FP64 (well above the FP32 error
+// of r^2 from exact fixed-point differences, ~3e-7, plus the 2^-26 A position rounding).
+constexpr double kBand = 1e-6;
+constexpr int kBandQueue = 64;   // band pairs a tile wave queues per home group
+constexpr int kBandSteps = 8;    // candidate steps with band pairs a tile wave records per group
+
 // Values that are the same on every lane, moved to scalar registers.
 __device__ inline int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
 __device__ inline double uni(double x) {
@@ -55,16 +66,77 @@ __device__ inline P pick(const P* a, int t) {
   return t == 0 ? a[0] : (t == 1 ? a[1] : (t == 2 ? a[2] : a[3]));
 }
 
+// Cutoff band, in the fixed-point units of r2s (2^-50 A^2).  The FP32 path counts a pair
+// as inside when r2s < hi.  Pairs with lo <= r2s < hi are in the band: there the FP32
+// r^2 cannot tell the side of the cutoff, so each is re-decided in FP64 and, if the FP64
+// test puts it outside, its force is taken back out (remove_band_pair).
+struct Band {
+  float lo, hi;
+};
+__device__ inline Band make_band(double rc2) {
+  return Band{(float)(rc2 * kFix * kFix * (1.0 - kBand)), (float)(rc2 * kFix * kFix * (1.0 + kBand))};
+}
+__device__ __forceinline__ bool in_band(float r2s, bool keep, const Band& b) {
+  return keep && r2s >= b.lo && r2s < b.hi;
+}
+
+// Exact cutoff test for a band pair (about one candidate in 10^6): r^2 < rc^2 decided from
+// the FP64 positions with the operation order of a plain FP64 evaluation (no fused
+// multiply-add), so the pair set is the FP64 one.  The image shift uses t * (1/L); it can
+// differ from rint(t / L) only for |t| ~ L/2, i.e. |d| ~ L/2 >= 1.5 rc, never for a pair
+// near the cutoff.  Returns the minimum-image difference and r^2.
+__device__ __forceinline__ bool inside_cutoff_f64(const double* __restrict__ pos, int64_t n, const BoxDev& B,
+                                                  int32_t i, int32_t j, double rc2, double (&d)[3], double& r2) {
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const double t = __dadd_rn(pos[q * n + i], -pos[q * n + j]);
+    d[q] = __dadd_rn(t, -__dmul_rn(B.L[q], rint(__dmul_rn(t, B.invL[q]))));
+    r2 = q == 0 ? __dmul_rn(d[q], d[q]) : __dadd_rn(r2, __dmul_rn(d[q], d[q]));
+  }
+  return r2 < rc2;
+}
+
+// Takes a band pair that the FP64 test puts outside back out of accumulators in units of
+// 2^25.  The pair sits at r ~ rc, where the force is ~|F(rc)|; evaluating it from the
+// FP64 difference instead of the fixed-point one leaves a residue ~1e-7 of that.
+template <bool ENERGY>
+__device__ __forceinline__ void remove_band_pair(const double (&d)[3], double r2, float f12, float f6, float e12,
+                                                 float e6, float ecut, float& ax, float& ay, float& az, double& e,
+                                                 double& es, double& w) {
+  const float r2i = 1.0f / (float)r2;
+  const float r6 = r2i * r2i * r2i;
+  const float g = r6 * (f12 * r6 - f6);
+  const float ffs = g * r2i * (float)kFix;
+  ax -= ffs * (float)d[0];
+  ay -= ffs * (float)d[1];
+  az -= ffs * (float)d[2];
+  if (ENERGY) {
+    const float en = r6 * (e12 * r6 - e6);
+    e -= (double)en;
+    es -= (double)en - (double)ecut;
+    w -= (double)g;
+  }
+}
+
+// FP32 r^2 of an exact fixed-point difference (units of 2^-50 A^2).  Written with explicit
+// fused multiply-adds so that every call site rounds identically.
+__device__ __forceinline__ float r2_fix(float dx, float dy, float dz) {
+  return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+}
+
 // One pair, mixed precision.  d* are exact fixed-point differences x_i - x_j; the force
 // accumulated in a* is in units of 2^25 (the caller scales the final sum by 2^-25).
-// BRANCHLESS evaluates the force for every lane and zeroes it outside the cutoff.
-template <bool ENERGY, bool BRANCHLESS = false>
-__device__ __forceinline__ void pair_fix(int dqx, int dqy, int dqz, bool keep, float rc2s, float f12,
-                                         float f6, float e12, float e6, float ecut, float& ax, float& ay,
-                                         float& az, double& e, double& es, double& w) {
+// Pairs in the cutoff band are counted; bmax keeps the bits of the largest r2s counted
+// (r2s >= 0, so integer order is float order), so that the caller sees a band pair
+// (bmax >= lo) at one integer max per pair and settles it.
+// Returns r2s.  BRANCHLESS evaluates the force for every lane and zeroes it outside.
+template <bool ENERGY, bool BRANCHLESS>
+__device__ __forceinline__ float pair_fix(int dqx, int dqy, int dqz, bool keep, const Band& bd, float f12,
+                                          float f6, float e12, float e6, float ecut, float& ax, float& ay,
+                                          float& az, double& e, double& es, double& w, int32_t& bmax) {
   const float dx = (float)dqx, dy = (float)dqy, dz = (float)dqz;
-  const float r2s = dx * dx + dy * dy + dz * dz;     // units of 2^-50 A^2
-  const bool hit = keep && r2s < rc2s;
+  const float r2s = r2_fix(dx, dy, dz);
+  const bool hit = keep && r2s < bd.hi;
   if (BRANCHLESS || hit) {
     const float r2 = r2s * kInvFix2F;
     const float r2i = rcp_f(r2);
@@ -75,6 +147,7 @@ __device__ __forceinline__ void pair_fix(int dqx, int dqy, int dqz, bool keep, f
     ax += ffs * dx;
     ay += ffs * dy;
     az += ffs * dz;
+    bmax = max(bmax, __float_as_int(BRANCHLESS ? (hit ? r2s : 0.0f) : r2s));
     if (ENERGY && hit) {
       const float en = r6 * (e12 * r6 - e6);
       e += (double)en;
@@ -82,6 +155,7 @@ __device__ __forceinline__ void pair_fix(int dqx, int dqy, int dqz, bool keep, f
       w += (double)g;
     }
   }
+  return r2s;
 }
 
 // One pair, FP64.
@@ -142,7 +216,7 @@ __global__ __launch_bounds__(kLjAtomBlock) void k_lj_atom(Views v, FFDev ff, LjP
   const PayT* __restrict__ pay = static_cast<const PayT*>(v.payload);
   const int32_t* __restrict__ cstart = v.cell_start;
   const int R = v.R;
-  const float rc2s = (float)(ff.rc2 * kFix * kFix);
+  const Band bd = make_band(ff.rc2);
   double e = 0.0, es = 0.0, w = 0.0;
   if (active) {
     const int64_t s = (int64_t)B.atom_off + local;
@@ -190,8 +264,14 @@ __global__ __launch_bounds__(kLjAtomBlock) void k_lj_atom(Views v, FFDev ff, LjP
               const int32_t tj = pay_tag(pj);
               const bool keep = (uint32_t)(tag_index(tj) - lo) > span;
               const int tt = ff.uniform_lj ? 0 : ti * 2 + tag_type(tj);
-              pair_fix<ENERGY>(hx - pj.x, hy - pj.y, hz - pj.z, keep, rc2s, pick(cf.f12, tt), pick(cf.f6, tt),
-                               pick(cf.e12, tt), pick(cf.e6, tt), pick(cf.ecut, tt), fx, fy, fz, e, es, w);
+              int32_t bmax = 0;
+              const float r2s = pair_fix<ENERGY, false>(hx - pj.x, hy - pj.y, hz - pj.z, keep, bd, pick(cf.f12, tt),
+                                                        pick(cf.f6, tt), pick(cf.e12, tt), pick(cf.e6, tt),
+                                                        pick(cf.ecut, tt), fx, fy, fz, e, es, w, bmax);
+              double d[3], r2;
+              if (in_band(r2s, keep, bd) && !inside_cutoff_f64(v.pos, v.N, B, i, tag_index(tj), ff.rc2, d, r2))
+                remove_band_pair<ENERGY>(d, r2, pick(cf.f12, tt), pick(cf.f6, tt), pick(cf.e12, tt),
+                                         pick(cf.e6, tt), pick(cf.ecut, tt), fx, fy, fz, e, es, w);
             }
           }
         }
@@ -219,6 +299,182 @@ struct Piece {
 };
 constexpr int kMaxPieces = 2 * (2 * kTileMaxR + 1) * (2 * kTileMaxR + 1);
 
+// Candidate t of a piece, moved into the home cell's frame (x-offset from its cell tag).
+template <bool FP64, typename PayT, typename Q>
+__device__ __forceinline__ void fetch_candidate(const PayT* __restrict__ pay, const Piece& pc, int t, const BoxDev& B,
+                                                Q ex, Q& jx, Q& jy, Q& jz, int32_t& jt) {
+  const PayT q = pay[t];
+  jt = pay_tag(q);
+  const int ox = pc.ox0 + ((tag_cx(jt) - pc.cx0) & 7);
+  if constexpr (FP64) {
+    jx = q.x + ox * B.edge[0];
+    jy = q.y + pc.oy * B.edge[1];
+    jz = q.z + pc.oz * B.edge[2];
+  } else {
+    jx = q.x + ox * ex;
+    jy = q.y + pc.oy * B.edge_q[1];
+    jz = q.z + pc.oz * B.edge_q[2];
+  }
+}
+
+// Stencil rows of home cell lc -> contiguous pieces of the sorted arrays (a row that wraps
+// in x is split in two), written to pcs in lane order.  Returns their number (the same on
+// every lane).
+__device__ __forceinline__ int build_pieces(const Views& v, const BoxDev& B, int lc, bool wact, Piece* pcs) {
+  const int ln = lane();
+  const int R = v.R, W = 2 * R + 1;
+  const int M0 = B.M[0], M1 = B.M[1], M2 = B.M[2];
+  const int kx = lc % M0, ky = (lc / M0) % M1, kz = lc / (M0 * M1);
+  const int32_t* __restrict__ cs = v.cell_start;
+  Piece p1{0, 0, 0, 0, 0, 0}, p2{0, 0, 0, 0, 0, 0};
+  int has = 0;
+  if (wact && ln < W * W) {
+    const int oy = ln % W - R, oz = ln / W - R;
+    int ny = ky + oy;
+    ny += ny < 0 ? M1 : 0;
+    ny -= ny >= M1 ? M1 : 0;
+    int nz = kz + oz;
+    nz += nz < 0 ? M2 : 0;
+    nz -= nz >= M2 ? M2 : 0;
+    const int row = B.cell_off + M0 * (ny + M1 * nz);
+    const int xa = kx - R, xb = kx + R;
+    if (xa >= 0 && xb < M0) {
+      p1 = Piece{cs[row + xa], cs[row + xb + 1] - cs[row + xa], -R, xa, oy, oz};
+      has = 1;
+    } else if (xa < 0) {
+      p1 = Piece{cs[row + xa + M0], cs[row + M0] - cs[row + xa + M0], -R, xa + M0, oy, oz};
+      p2 = Piece{cs[row], cs[row + xb + 1] - cs[row], -kx, 0, oy, oz};
+      has = 2;
+    } else {
+      p1 = Piece{cs[row + xa], cs[row + M0] - cs[row + xa], -R, xa, oy, oz};
+      p2 = Piece{cs[row], cs[row + xb - M0 + 1] - cs[row], M0 - kx, 0, oy, oz};
+      has = 2;
+    }
+  }
+  const uint64_t m1 = __ballot(has >= 1), m2 = __ballot(has == 2);
+  const int idx = lanes_below(m1) + lanes_below(m2);
+  if (has >= 1) pcs[idx] = p1;
+  if (has == 2) pcs[idx + 1] = p2;
+  return __popcll(m1) + __popcll(m2);
+}
+
+struct BandEnergy {
+  double e, es, w;
+};
+
+// Settles the cutoff-band pairs of one home group of a mixed tile wave, after its home
+// forces are stored.  First the recorded candidate steps are revisited and their band
+// pairs queued in (step, home, lane) order; each queued pair is then re-decided in FP64
+// and, when outside, taken back out of the stored force of its home (summed per home over
+// the lanes, applied by the lane that stored that home).  With more steps or pairs than
+// the slots hold (not expected in a melt) the whole candidate set of each home is walked
+// again instead.  LDS executes a wave's accesses in order and only this wave wrote its
+// slots, so no barrier is needed.  Out of line: this runs for about one group in 100, and
+// inline it would raise the register count of the pair loop.
+template <bool ENERGY, bool UNI>
+__device__ __forceinline__ BandEnergy settle_band_group(const Views& v, int chain_len, int excl, double rc2,
+                                                     const LjPair<float>& cf, const BoxDev& B, Band bd,
+                                                     const Piece* pcs, int np, const int2 (*steps)[2],
+                                                     int32_t* bq, const int4* __restrict__ pay, int hs, int g0,
+                                                     int kc, int nsteps) {
+  const int ln = lane(), half = ln >> 5, hl = ln & 31;
+  const int ex = B.edge_q[0];
+  float* f = static_cast<float*>(v.f_lj);
+  double e = 0.0, es = 0.0, w = 0.0;
+  int qn = 0;
+  if (nsteps <= kBandSteps) {
+    for (int s = 0; s < nsteps; ++s) {
+      const int2 po = steps[s][half];
+      Piece pc{0, 0, 0, 0, 0, 0};
+      if (po.x < np) pc = pcs[po.x];
+      const bool act = po.x < np && po.y + hl < pc.count;
+      int jx = 0, jy = 0, jz = 0;
+      int32_t jt = 0;
+      if (act) fetch_candidate<false>(pay, pc, pc.start + po.y + hl, B, ex, jx, jy, jz, jt);
+      for (int k = 0; k < kc; ++k) {
+        const int4 hq = pay[hs + g0 + k];
+        const int32_t i = tag_index(pay_tag(hq));
+        const int32_t c0 = i - i % chain_len;
+        const int32_t hlo = max(i - excl, c0);
+        const uint32_t hspan = (uint32_t)(min(i + excl, c0 + chain_len - 1) - hlo);
+        const bool keep = act && (uint32_t)(tag_index(jt) - hlo) > hspan;
+        const bool qb = in_band(r2_fix((float)(hq.x - jx), (float)(hq.y - jy), (float)(hq.z - jz)), keep, bd);
+        const uint64_t qm = __ballot(qb);
+        const int at = qn + lanes_below(qm);
+        if (qb && at < kBandQueue) bq[at] = (tag_index(jt) << 4) | (tag_type(jt) << 3) | k;
+        qn += __popcll(qm);
+      }
+    }
+  }
+  if (nsteps <= kBandSteps && qn <= kBandQueue) {
+    float bx = 0.0f, by = 0.0f, bz = 0.0f;
+    int kq = -1;
+    if (ln < qn) {
+      const int32_t ent = bq[ln];
+      const int32_t htag = pay_tag(pay[hs + g0 + (ent & 7)]);
+      double d[3], r2;
+      if (!inside_cutoff_f64(v.pos, v.N, B, tag_index(htag), ent >> 4, rc2, d, r2)) {
+        const int tt = UNI ? 0 : tag_type(htag) * 2 + ((ent >> 3) & 1);
+        remove_band_pair<ENERGY>(d, r2, pick(cf.f12, tt), pick(cf.f6, tt), pick(cf.e12, tt), pick(cf.e6, tt),
+                                 pick(cf.ecut, tt), bx, by, bz, e, es, w);
+        kq = ent & 7;
+      }
+    }
+    for (int k = 0; k < kc; ++k) {
+      if (__ballot(kq == k) == 0) continue;
+      float sx = kq == k ? bx : 0.0f, sy = kq == k ? by : 0.0f, sz = kq == k ? bz : 0.0f;
+      for (int off = 32; off > 0; off >>= 1) {
+        sx += __shfl_xor(sx, off);
+        sy += __shfl_xor(sy, off);
+        sz += __shfl_xor(sz, off);
+      }
+      if (ln == k) {
+        const int32_t i = tag_index(pay_tag(pay[hs + g0 + k]));
+        f[i] += sx * kInvFixF;
+        f[v.N + i] += sy * kInvFixF;
+        f[2 * v.N + i] += sz * kInvFixF;
+      }
+    }
+  } else {
+    for (int k = 0; k < kc; ++k) {
+      const int4 hq = pay[hs + g0 + k];
+      const int32_t i = tag_index(pay_tag(hq));
+      const int32_t c0 = i - i % chain_len;
+      const int32_t hlo = max(i - excl, c0);
+      const uint32_t hspan = (uint32_t)(min(i + excl, c0 + chain_len - 1) - hlo);
+      float bx = 0.0f, by = 0.0f, bz = 0.0f;
+      for (int q = 0; q < np; ++q) {
+        const Piece pc = pcs[q];
+        for (int t = ln; t < pc.count; t += 64) {
+          int jx, jy, jz;
+          int32_t jt;
+          fetch_candidate<false>(pay, pc, pc.start + t, B, ex, jx, jy, jz, jt);
+          const int32_t jidx = tag_index(jt);
+          const float r2s = r2_fix((float)(hq.x - jx), (float)(hq.y - jy), (float)(hq.z - jz));
+          double d[3], r2;
+          if (in_band(r2s, (uint32_t)(jidx - hlo) > hspan, bd) &&
+              !inside_cutoff_f64(v.pos, v.N, B, i, jidx, rc2, d, r2)) {
+            const int tt = UNI ? 0 : tag_type(pay_tag(hq)) * 2 + tag_type(jt);
+            remove_band_pair<ENERGY>(d, r2, pick(cf.f12, tt), pick(cf.f6, tt), pick(cf.e12, tt),
+                                     pick(cf.e6, tt), pick(cf.ecut, tt), bx, by, bz, e, es, w);
+          }
+        }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        bx += __shfl_xor(bx, off);
+        by += __shfl_xor(by, off);
+        bz += __shfl_xor(bz, off);
+      }
+      if (ln == k) {
+        f[i] += bx * kInvFixF;
+        f[v.N + i] += by * kInvFixF;
+        f[2 * v.N + i] += bz * kInvFixF;
+      }
+    }
+  }
+  return BandEnergy{e, es, w};
+}
+
 template <bool FP64, bool ENERGY, bool UNI, int KMAX, bool BRANCHLESS>
 __global__ __launch_bounds__(64 * kTileWaves) void k_lj_tile(Views v, FFDev ff, LjPair<float> cf,
                                                              LjPair<double> cd) {
@@ -226,8 +482,9 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_lj_tile(Views v, FFDev ff, 
   using P = std::conditional_t<FP64, double, float>;
   using Q = std::conditional_t<FP64, double, int>;     // coordinate type
   __shared__ Piece pieces[kTileWaves][kMaxPieces];
-  __shared__ int npieces[kTileWaves];
   __shared__ dd red[kTileWaves][3];
+  __shared__ int32_t bq[kTileWaves][kBandQueue];   // queued band pairs: j << 4 | type_j << 3 | k
+  __shared__ int2 bsteps[kTileWaves][kBandSteps][2];   // (piece, offset) of each half at a band step
 
   const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   const int ln = lane(), half = ln >> 5, hl = ln & 31;
@@ -240,54 +497,17 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_lj_tile(Views v, FFDev ff, 
   const BoxDev& B = v.boxes[b];
   const int lc = (blk - B.lj_blk_off) * kTileWaves + wave;   // home cell within the box
   const bool wact = lc < B.n_cells;
-  const int R = v.R, W = 2 * R + 1;
-  const int M0 = B.M[0], M1 = B.M[1], M2 = B.M[2];
-  const int kx = lc % M0, ky = (lc / M0) % M1, kz = lc / (M0 * M1);
   const int32_t* __restrict__ cs = v.cell_start;
   const PayT* __restrict__ pay = static_cast<const PayT*>(v.payload);
 
-  // ---- stencil rows -> contiguous pieces of the sorted arrays (split at the x wrap)
-  {
-    Piece p1{0, 0, 0, 0, 0, 0}, p2{0, 0, 0, 0, 0, 0};
-    int has = 0;
-    if (wact && ln < W * W) {
-      const int oy = ln % W - R, oz = ln / W - R;
-      int ny = ky + oy;
-      ny += ny < 0 ? M1 : 0;
-      ny -= ny >= M1 ? M1 : 0;
-      int nz = kz + oz;
-      nz += nz < 0 ? M2 : 0;
-      nz -= nz >= M2 ? M2 : 0;
-      const int row = B.cell_off + M0 * (ny + M1 * nz);
-      const int xa = kx - R, xb = kx + R;
-      if (xa >= 0 && xb < M0) {
-        p1 = Piece{cs[row + xa], cs[row + xb + 1] - cs[row + xa], -R, xa, oy, oz};
-        has = 1;
-      } else if (xa < 0) {
-        p1 = Piece{cs[row + xa + M0], cs[row + M0] - cs[row + xa + M0], -R, xa + M0, oy, oz};
-        p2 = Piece{cs[row], cs[row + xb + 1] - cs[row], -kx, 0, oy, oz};
-        has = 2;
-      } else {
-        p1 = Piece{cs[row + xa], cs[row + M0] - cs[row + xa], -R, xa, oy, oz};
-        p2 = Piece{cs[row], cs[row + xb - M0 + 1] - cs[row], M0 - kx, 0, oy, oz};
-        has = 2;
-      }
-    }
-    const uint64_t m1 = __ballot(has >= 1), m2 = __ballot(has == 2);
-    const uint64_t below = (1ull << ln) - 1ull;
-    const int idx = __popcll(m1 & below) + __popcll(m2 & below);
-    if (has >= 1) pieces[wave][idx] = p1;
-    if (has == 2) pieces[wave][idx + 1] = p2;
-    if (ln == 0) npieces[wave] = __popcll(m1) + __popcll(m2);
-  }
+  const int np = build_pieces(v, B, lc, wact, pieces[wave]);
   __syncthreads();
 
   double e = 0.0, es = 0.0, w = 0.0;
   if (wact) {
     const int hs = __builtin_amdgcn_readfirstlane(cs[B.cell_off + lc]);
     const int hn = __builtin_amdgcn_readfirstlane(cs[B.cell_off + lc + 1]) - hs;
-    const int np = __builtin_amdgcn_readfirstlane(npieces[wave]);
-    const float rc2s = (float)(ff.rc2 * kFix * kFix);
+    const Band bd = make_band(ff.rc2);
     const Q ex = FP64 ? (Q)0 : (Q)B.edge_q[0];
     for (int g0 = 0; g0 < hn; g0 += KMAX) {
       const int kc = min(KMAX, hn - g0);
@@ -320,11 +540,13 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_lj_tile(Views v, FFDev ff, 
         } else {
           hx[k] = hy[k] = hz[k] = (Q)0;
           lo[k] = 0;
-          span[k] = 0;
+          span[k] = 0xffffffffu;   // excludes every candidate
           hti[k] = 0;
         }
       }
       // two candidate streams, one per 32-lane half: pieces half, half+2, half+4, ...
+      int nsteps = 0;       // candidate steps with a band pair (wave-uniform)
+      int32_t bmax = 0;     // bits of the largest r2s counted since the last band check
       int p = half, o = 0;
       while (true) {
         const bool hv = p < np;
@@ -334,21 +556,7 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_lj_tile(Views v, FFDev ff, 
         const bool act = hv && (o + hl < pc.count);
         Q jx = (Q)0, jy = (Q)0, jz = (Q)0;
         int32_t jt = 0;
-        if (act) {
-          const PayT q = pay[pc.start + o + hl];
-          jt = pay_tag(q);
-          const int ox = pc.ox0 + ((tag_cx(jt) - pc.cx0) & 7);
-          // candidate in the home cell's frame
-          if constexpr (FP64) {
-            jx = q.x + ox * B.edge[0];
-            jy = q.y + pc.oy * B.edge[1];
-            jz = q.z + pc.oz * B.edge[2];
-          } else {
-            jx = q.x + ox * ex;
-            jy = q.y + pc.oy * B.edge_q[1];
-            jz = q.z + pc.oz * B.edge_q[2];
-          }
-        }
+        if (act) fetch_candidate<FP64>(pay, pc, pc.start + o + hl, B, ex, jx, jy, jz, jt);
         const int32_t jidx = tag_index(jt);
         const int jtype = tag_type(jt);
 #pragma unroll
@@ -360,10 +568,19 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_lj_tile(Views v, FFDev ff, 
               pair_f64<ENERGY>(hx[k] - jx, hy[k] - jy, hz[k] - jz, keep, ff.rc2, pick(cd.f12, tt),
                                pick(cd.f6, tt), pick(cd.e12, tt), pick(cd.e6, tt), pick(cd.ecut, tt), ax[k],
                                ay[k], az[k], e, es, w);
-            else
-              pair_fix<ENERGY, BRANCHLESS>(hx[k] - jx, hy[k] - jy, hz[k] - jz, keep, rc2s, pick(cf.f12, tt),
-                                           pick(cf.f6, tt), pick(cf.e12, tt), pick(cf.e6, tt),
-                                           pick(cf.ecut, tt), ax[k], ay[k], az[k], e, es, w);
+            else {
+              pair_fix<ENERGY, BRANCHLESS>(hx[k] - jx, hy[k] - jy, hz[k] - jz, keep, bd, pick(cf.f12, tt),
+                                           pick(cf.f6, tt), pick(cf.e12, tt), pick(cf.e6, tt), pick(cf.ecut, tt),
+                                           ax[k], ay[k], az[k], e, es, w, bmax);
+            }
+          }
+        }
+        if constexpr (!FP64) {
+          // rare: a lane counted a pair in the cutoff band; note where both halves were
+          if (__builtin_amdgcn_ballot_w64(bmax >= __float_as_int(bd.lo)) != 0) {
+            bmax = 0;
+            if (nsteps < kBandSteps && hl == 0) bsteps[wave][nsteps][half] = make_int2(p, o);
+            ++nsteps;
           }
         }
         o += 32;
@@ -396,6 +613,18 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_lj_tile(Views v, FFDev ff, 
           }
         }
       }
+      if constexpr (!FP64) {
+        if (nsteps > 0) {
+          const BandEnergy be = settle_band_group<ENERGY, UNI>(v, ff.chain_len, ff.excl, ff.rc2, cf, B, bd,
+                                                               pieces[wave], np, bsteps[wave], bq[wave], pay, hs,
+                                                               g0, kc, nsteps);
+          if (ENERGY) {
+            e += be.e;
+            es += be.es;
+            w += be.w;
+          }
+        }
+      }
     }
   }
   if (ENERGY) block_energy<kTileWaves>(e, es, w, red, v.part_lj + (int64_t)blk * 3);
@@ -418,7 +647,7 @@ template <bool FP64, bool ENERGY>
 void launch_tile(const Views& v, const FFDev& ff, const LjPair<float>& cf, const LjPair<double>& cd,
                  bool branchless, hipStream_t s) {
   dim3 g((v.n_lj_blocks + kXcds - 1) / kXcds * kXcds), b(64 * kTileWaves);
-  constexpr int K = FP64 ? 4 : 8;
+  constexpr int K = FP64 ? 4 : kTileHomesMixed;
   if (ff.uniform_lj) {
     if (branchless)
       hipLaunchKernelGGL((k_lj_tile<FP64, ENERGY, true, K, true>), g, b, 0, s, v, ff, cf, cd);

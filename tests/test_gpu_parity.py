@@ -175,6 +175,39 @@ def test_general_types_and_dihedral_phase(ff, melt):
             s.close()
 
 
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+@pytest.mark.parametrize("R,kernel", [(1, 1), (1, 2), (2, 2), (2, 3)])
+def test_pairs_at_the_cutoff(ff, precision, R, kernel):
+    """Two straight 8-atom chains side by side, atom k of one facing atom k of the other at
+    r = rc (1 + delta_k), delta_k from -4e-7 to +4e-7: inside the FP32 uncertainty of r^2.
+    The LJ pair set must be the FP64 one: each facing pair adds |F(rc)| ~ 3e-4 kcal/mol/A
+    or nothing, so every atom's LJ force is compared with the oracle far below that."""
+    rc = ff["rc"]
+    deltas = np.array([-4e-7, -2e-7, -5e-8, -1e-8, 1e-8, 5e-8, 2e-7, 4e-7])
+    n = deltas.size
+    x = 5.0 + 1.53 * np.arange(n)
+    pos = np.zeros((3, 2 * n))
+    pos[0] = np.concatenate([x, x])
+    pos[1] = np.concatenate([np.full(n, 5.0), 5.0 + rc * (1.0 + deltas)])
+    pos[2] = 5.0
+    box = np.array([40.0, 40.0, 40.0])
+    types = np.zeros(2 * n, dtype=np.uint8)
+    fo, _ = O.lj_brute(ff, pos, types, box, n)
+    # the oracle's own decision: the facing pair counts iff delta < 0
+    d = pos[:, n:] - pos[:, :n]
+    inside = np.sum(d * d, axis=0) < rc * rc
+    assert np.array_equal(inside, deltas < 0)
+    from paper_1001_3764_amd.md import MDSystem
+    print("cutoff pairs: precision=%s R=%d kernel=%d" % (precision, R, kernel), flush=True)
+    s = MDSystem(ff, [2], box[None, :], [0.0], pos, np.zeros_like(pos), types, chain_len=n,
+                 precision=precision, cell_div=R, lj_kernel=kernel)
+    flj = s.forces(lj_only=True)
+    s.close()
+    s6 = ff["sigma"][0] ** 6
+    f_rc = 4 * ff["epsilon"][0] * (12 * s6 * s6 / rc ** 13 - 6 * s6 / rc ** 7)
+    assert np.max(np.abs(flj - fo)) < 0.02 * abs(f_rc)
+
+
 def _ensemble(n_boxes=3):
     melts = [make_melt(c, density=0.80, T=300.0 + 50 * k, seed_melt=900 + k, seed_vel=950 + k, jitter=0.05)
              for k, c in enumerate((4, 11, 7)[:n_boxes])]
