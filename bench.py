@@ -8,6 +8,11 @@ kernel), the force error of the mixed form against the FP64 oracle (at the grown
 at the end of the timed run), per-phase kernel times, the roofline position of the
 Lennard-Jones kernel, and the FP64 CPU oracle timed on a bounded sample of the workload.
 
+``--workload`` selects one of the other presets instead (their own JSON line, same keys):
+melt3M_mixed (NVT throughput, then the NVE energy drift over 1,000 steps), ensemble64_mixed
+(64 boxes in one launch sequence, the smallest box checked against the oracle) or
+melt30M_mixed (throughput and per-kernel algorithmic HBM rates at 30M atoms).
+
 Prints ONE JSON line.  Inputs are synthetic (seeded melts); see pe_melt.
 """
 
@@ -109,11 +114,16 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first copy a device buffer of this many MiB (HBM counter calibration)")
+    ap.add_argument("--workload", default="melt300k_mixed",
+                    choices=["melt300k_mixed", "melt3M_mixed", "ensemble64_mixed", "melt30M_mixed"])
+    ap.add_argument("--nve-steps", type=int, default=1000, help="melt3M_mixed: NVE drift window")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (one process, no collectives); --gpus %d is not supported"
               % args.gpus, flush=True)
         sys.exit(2)
+    if args.workload != "melt300k_mixed":
+        return run_other_workload(args)
 
     import numpy as np
     import torch
@@ -257,6 +267,138 @@ def main():
         "final_temperature_K": e_end["temperature"],
         "roofline": roofline,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+# Algorithmic HBM bytes per atom of the per-atom phases (mixed form; see the kernel table of
+# the design notes): integrate+bin, scatter, rank+payload, bonded+kick.
+ALGO_BYTES_PER_ATOM = {"integrate_bin": 117, "scatter": 16, "rank_payload": 61, "bonded_kick": 97}
+
+
+def run_other_workload(args):
+    """The non-default presets: same JSON keys, their own extra fields."""
+    import numpy as np
+    import torch
+
+    from paper_1001_3764_amd.md import MDSystem
+    from pe_melt import WORKLOADS, build_melts, polyethylene_forcefield
+
+    wl = WORKLOADS[args.workload]
+    ff = polyethylene_forcefield()
+    dev = torch.device("cuda:0")
+    t = time.perf_counter()
+    melts = build_melts(wl, threads=16)
+    N = sum(m.n_atoms for m in melts)
+    log("%s: %d box(es), %d atoms (%.1fs)" % (wl.name, len(melts), N, time.perf_counter() - t))
+    pos = np.concatenate([m.pos for m in melts], axis=1)
+    vel = np.concatenate([m.vel for m in melts], axis=1)
+    types = np.concatenate([m.types for m in melts])
+    boxes = np.stack([m.box for m in melts])
+    chains = [m.n_chains for m in melts]
+
+    def make(precision, T0, p=pos, v=vel, graph=not args.no_graph):
+        return MDSystem(ff, chains, boxes, T0, p, v, types, chain_len=wl.chain_len, dt=wl.dt_fs,
+                        tau=wl.tau_fs, precision=precision, cell_div=args.cell_div, lj_kernel=args.lj_kernel,
+                        use_graph=graph, device=dev)
+
+    steps = args.steps if args.steps != 10000 else wl.steps   # the preset's own length by default
+    s = make("mixed", list(wl.T0))
+    R, kern = s.tuning()
+    s.step(args.warmup)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize(dev)
+    wall = time.perf_counter() - t0
+    value = N * steps / wall
+    ms_per_step = 1e3 * wall / steps
+    energies = s.energies()
+    log("mixed: R=%d kernel %d, %.3f ms/step, %.3e atom-steps/s" % (R, kern, ms_per_step, value))
+    n_prof = min(steps, 200)
+    phases = {k: v / n_prof for k, v in s.step_timed(n_prof).items()}
+    hbm = {k: round(ALGO_BYTES_PER_ATOM[k] * N / (phases[k] * 1e-3) / 1e9, 1) for k in ALGO_BYTES_PER_ATOM}
+    extra = {"phases_ms_avg": {k: round(v, 5) for k, v in phases.items()},
+             "algorithmic_hbm_GBps_per_phase": hbm,
+             "final_temperature_K": [round(e["temperature"], 3) for e in energies][:8]}
+
+    if wl.name == "melt3M_mixed":
+        # NVE energy drift from the NVT end state, mixed and FP64, both graph-replayed
+        p_end, v_end = s.state()
+        s.close()
+        drift = {}
+        for precision in ("mixed", "fp64"):
+            sn = make(precision, [0.0], p_end, v_end)
+            rows = []
+            for k in range(args.nve_steps // 100 + 1):
+                if k:
+                    sn.step(100)
+                e = sn.energies()[0]
+                rows.append((100 * k, e["e_kin"] + e["e_lj"] + e["e_bond"] + e["e_angle"] + e["e_dih"],
+                             e["e_kin"] + e["e_lj_shifted"] + e["e_bond"] + e["e_angle"] + e["e_dih"],
+                             e["temperature"]))
+            sn.close()
+            r = np.array(rows)
+            slope = np.polyfit(r[:, 0], r[:, 1], 1)[0]
+            slope_s = np.polyfit(r[:, 0], r[:, 2], 1)[0]
+            ke0 = 1.5 * N * 1.987204259e-3 * r[0, 3]
+            drift[precision] = {
+                "steps": args.nve_steps, "E_total_start_kcal_mol": r[0, 1], "E_total_end_kcal_mol": r[-1, 1],
+                "drift_kcal_mol_per_atom_per_ns": slope / N * 1e6 / wl.dt_fs,
+                "drift_shifted_kcal_mol_per_atom_per_ns": slope_s / N * 1e6 / wl.dt_fs,
+                "max_abs_dev_over_KE": float(np.max(np.abs(r[:, 1] - r[0, 1])) / ke0),
+                "T_K": [round(x, 3) for x in r[:, 3]]}
+            log("NVE %s: drift %.3e (shifted %.3e) kcal/mol/atom/ns, max |E - E0| / KE %.2e"
+                % (precision, drift[precision]["drift_kcal_mol_per_atom_per_ns"],
+                   drift[precision]["drift_shifted_kcal_mol_per_atom_per_ns"], drift[precision]["max_abs_dev_over_KE"]))
+        extra["nve_drift"] = drift
+    else:
+        s.close()
+
+    if wl.name == "ensemble64_mixed":
+        # the smallest box against the oracle, in a fresh context (same launch sequence)
+        import oracle as O
+        O.set_threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+        b = int(np.argmin([m.n_atoms for m in melts]))
+        m = melts[b]
+        off = sum(x.n_atoms for x in melts[:b])
+        sc = make("mixed", list(wl.T0))
+        f = sc.forces()[:, off:off + m.n_atoms]
+        sc.close()
+        fo, _ = O.forces(ff, m.pos, m.types, m.box, m.chain_len)
+        fn = np.sqrt(np.sum(fo ** 2, axis=0))
+        err = float(np.max(np.sqrt(np.sum((f - fo) ** 2, axis=0)) / np.maximum(fn, np.sqrt(np.mean(fn ** 2)))))
+        extra["smallest_box"] = {"box": b, "atoms": m.n_atoms, "force_max_rel_err_vs_oracle": err}
+        log("smallest box %d (%d atoms): force error %.3e" % (b, m.n_atoms, err))
+
+    plain = None
+    if not args.no_fp64:
+        fp_steps = min(args.fp64_steps, 200)
+        s64 = make("fp64", list(wl.T0), graph=False)
+        s64.step(10)
+        torch.cuda.synchronize(dev)
+        a = time.perf_counter()
+        s64.step(fp_steps)
+        torch.cuda.synchronize(dev)
+        b_ = time.perf_counter()
+        plain = {"value": N * fp_steps / (b_ - a), "unit": "atom-steps/s", "steps": fp_steps,
+                 "ms_per_step": 1e3 * (b_ - a) / fp_steps, "tuning": list(s64.tuning()), "graph": False}
+        s64.close()
+        log("fp64: %.3f ms/step, %.3e atom-steps/s" % (plain["ms_per_step"], plain["value"]))
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "atom-steps/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": wl.name, "boxes": len(melts), "atoms": N, "chains": int(sum(chains)),
+                   "chain_len": wl.chain_len, "density_g_cm3": wl.density, "tiles": wl.tiles,
+                   "T0_K": [wl.T0[0], wl.T0[-1]], "thermostat": "berendsen", "tau_fs": wl.tau_fs,
+                   "dt_fs": wl.dt_fs, "precision": "mixed (FP32 force, FP64 state)", "cell_div": R,
+                   "lj_kernel": kern, "graph": not args.no_graph, "bins_rebuilt_every_step": True},
+        "ns_per_day": (1e3 / ms_per_step) * wl.dt_fs * 86400 * 1e-6,
+        "plain_fp64_gpu": plain,
+        "speedup_vs_plain_fp64": (value / plain["value"]) if plain else None,
+        **extra,
     }
     print(json.dumps(out), flush=True)
 

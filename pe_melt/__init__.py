@@ -4,9 +4,9 @@ Shared as input data by the CPU reference (``oracle/``) and the GPU library; it 
 none of the simulation's arithmetic.
 """
 
-from .configs import WORKLOADS, Workload
+from .configs import WORKLOADS, Workload, build_melts
 from .forcefield import polyethylene_forcefield, table_i_in_kcal_angstrom
-from .generator import Melt, box_length, make_melt, unwrap_chains, wrap_positions
+from .generator import Melt, box_length, make_melt, make_tiled_melt, unwrap_chains, wrap_positions
 
-__all__ = ["WORKLOADS", "Workload", "Melt", "box_length", "make_melt", "unwrap_chains",
+__all__ = ["WORKLOADS", "Workload", "build_melts", "Melt", "box_length", "make_melt", "make_tiled_melt", "unwrap_chains",
            "wrap_positions", "polyethylene_forcefield", "table_i_in_kcal_angstrom"]

@@ -25,6 +25,7 @@ class Workload:
     chain_len: int = 300
     dt_fs: float = 1.0
     tau_fs: float = 100.0
+    tiles: int = 1             # > 1: each box is tiles^3 copies of a melt grown tiles x smaller
 
     @property
     def n_boxes(self) -> int:
@@ -51,10 +52,27 @@ WORKLOADS = {
                                ((2000, 2001),), "mixed"),
     # 10,000 chains, 3,000,000 atoms, 0.85 g/cm^3, 300 K NVT
     "melt3M_mixed": Workload("melt3M_mixed", (10000,), 0.85, (300.0,), (300.0,), 5000,
-                             ((3000, 3001),), "mixed"),
+                             ((3000, 3001),), "mixed", tiles=2),
     # 64 independent boxes of 20..400 chains at 250..450 K
     "ensemble64_mixed": _batched_ensemble(),
     # 100,000 chains, 30,000,000 atoms, 0.85 g/cm^3, 300 K NVT
     "melt30M_mixed": Workload("melt30M_mixed", (100000,), 0.85, (300.0,), (300.0,), 1000,
-                              ((5000, 5001),), "mixed"),
+                              ((5000, 5001),), "mixed", tiles=5),
 }
+
+
+def build_melts(wl: Workload, threads: int = 16) -> list:
+    """The seeded melt of every box of a workload.  Boxes are grown on a thread pool (the
+    C grower runs without the interpreter lock), so a 64-box ensemble takes seconds."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from .generator import make_melt, make_tiled_melt
+
+    def one(b: int):
+        sm, sv = wl.seeds[b]
+        if wl.tiles > 1:
+            return make_tiled_melt(wl.n_chains[b], wl.tiles, wl.chain_len, wl.density, wl.T_init[b], sm, sv)
+        return make_melt(wl.n_chains[b], wl.chain_len, wl.density, wl.T_init[b], sm, sv)
+
+    with ThreadPoolExecutor(max_workers=max(1, min(threads, wl.n_boxes))) as ex:
+        return list(ex.map(one, range(wl.n_boxes)))

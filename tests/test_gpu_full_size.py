@@ -1,0 +1,163 @@
+"""GPU parity at the full sizes of the benchmark workloads, in the launch configuration the
+benchmark times: mixed precision, autotuned stencil radius and LJ kernel, graph-replayed
+steps.  The oracle computes sampled atoms one by one where the whole system would take too
+long, and the whole system where it is cheap (bins, bonded terms, the smallest box)."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from pe_melt import WORKLOADS, build_melts
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5   # FP32 force error, per atom against max(|F_i|, F_rms)
+
+
+def rel_err(d, scale):
+    """max_i |d_i| / max(|scale_i|, rms_i |scale_i|) over atoms (columns)."""
+    fn = np.sqrt(np.sum(scale ** 2, axis=0))
+    frms = np.sqrt(np.mean(fn ** 2))
+    return float(np.max(np.sqrt(np.sum(d ** 2, axis=0)) / np.maximum(fn, frms)))
+
+
+def energy_close(e, ref, keys=("e_lj", "e_bond", "e_angle", "e_dih")):
+    """Relative 2e-6 of the whole potential energy: a grown melt starts with every bond and
+    angle at its minimum, where those terms are ~0 and a relative test of them alone is
+    meaningless."""
+    scale = sum(abs(ref[k]) for k in keys)
+    for k in keys:
+        assert e[k] == pytest.approx(ref[k], rel=2e-6, abs=2e-6 * scale), k
+
+
+def threads():
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def system(ff, melts, wl, precision="mixed", **kw):
+    from paper_1001_3764_amd.md import MDSystem
+    pos = np.concatenate([m.pos for m in melts], axis=1)
+    vel = np.concatenate([m.vel for m in melts], axis=1)
+    types = np.concatenate([m.types for m in melts])
+    boxes = np.stack([m.box for m in melts])
+    print("system %s: %d boxes, N=%d, %s %s" % (wl.name, len(melts), pos.shape[1], precision, kw), flush=True)
+    return MDSystem(ff, [m.n_chains for m in melts], boxes, list(wl.T0), pos, vel, types,
+                    chain_len=wl.chain_len, dt=wl.dt_fs, tau=wl.tau_fs, precision=precision, **kw)
+
+
+def check_bins(s, melt, b=0):
+    M, cell_off, atom_off = s.grid(b)
+    start, atoms = s.bins()
+    nc = int(np.prod(M))
+    cnt, ostart, oatoms = O.bin_atoms(O.cell_index(melt.pos, melt.box, M), nc)
+    lo, hi = start[cell_off], start[cell_off + nc]
+    np.testing.assert_array_equal(start[cell_off:cell_off + nc + 1] - lo, ostart)
+    np.testing.assert_array_equal(atoms[lo:hi] - atom_off, oatoms)
+
+
+def check_sampled_forces(ff, s, melt, n_sample, seed, atom_off=0, include_max=True):
+    f = s.forces()[:, atom_off:atom_off + melt.n_atoms]
+    flj = s.forces(lj_only=True)[:, atom_off:atom_off + melt.n_atoms]
+    fo_b, _ = O.bonded(ff, melt.pos, melt.box, melt.chain_len)
+    rng = np.random.default_rng(seed)
+    sample = rng.choice(melt.n_atoms, size=n_sample, replace=False)
+    if include_max:   # the atoms with the largest bonded force (forced contacts sit near them)
+        sample = np.unique(np.concatenate([sample, np.argsort(np.sum(fo_b ** 2, axis=0))[-50:]]))
+    fo_lj, _ = O.lj_cells(ff, melt.pos, melt.types, melt.box, melt.chain_len, subset=sample)
+    # each atom's error against its own total force (F_rms floor); the GPU total stands in for
+    # the oracle's where the oracle's LJ part is not computed (they agree to 1e-5)
+    err_lj = rel_err(flj[:, sample] - fo_lj, f[:, sample])
+    err_b = rel_err(f - flj - fo_b, f)
+    err = rel_err(f[:, sample] - fo_lj - fo_b[:, sample], fo_lj + fo_b[:, sample])
+    print("sampled force error (%d atoms): LJ %.3e bonded %.3e total %.3e" % (sample.size, err_lj, err_b, err))
+    assert err_lj <= TOL and err_b <= TOL and err <= TOL
+
+
+@pytest.fixture(scope="module")
+def melt300k():
+    O.set_threads(threads())
+    return build_melts(WORKLOADS["melt300k_mixed"], threads())[0]
+
+
+def test_melt300k_bins_forces_energies(ff, melt300k):
+    """300,000 atoms: bins bit-exact, every bonded force, 4,000 sampled LJ forces, and the
+    energies against the oracle's full sums."""
+    s = system(ff, [melt300k], WORKLOADS["melt300k_mixed"], cell_div=0, lj_kernel=0, use_graph=True)
+    print("tuned (R, kernel) =", s.tuning(), flush=True)
+    check_bins(s, melt300k)
+    check_sampled_forces(ff, s, melt300k, 4000, 17)
+    e = s.energies()[0]
+    _, eo = O.lj_cells(ff, melt300k.pos, melt300k.types, melt300k.box, 300)
+    _, eb = O.bonded(ff, melt300k.pos, melt300k.box, 300)
+    energy_close(e, {**eo, **eb})
+    assert e["e_lj_shifted"] == pytest.approx(eo["e_lj_shifted"], rel=2e-6)
+    s.close()
+
+
+def test_melt300k_first_100_steps(ff, melt300k):
+    """The Berendsen quench (500 -> 300 K), 100 graph-replayed steps: mixed and plain FP64 GPU
+    forms against the oracle's own 100 steps."""
+    wl = WORKLOADS["melt300k_mixed"]
+    f0, _ = O.forces(ff, melt300k.pos, melt300k.types, melt300k.box, 300)
+    po, vo, _, eo = O.run(ff, melt300k.pos, melt300k.vel, f0, melt300k.types, melt300k.box, 300, 100,
+                          dt=wl.dt_fs, tau=wl.tau_fs, T0=wl.T0[0])
+    out = {}
+    for precision in ("mixed", "fp64"):
+        s = system(ff, [melt300k], wl, precision, cell_div=0, lj_kernel=0, use_graph=True)
+        s.step(100)
+        p, v = s.state()
+        T = s.energies()[0]["temperature"]
+        s.close()
+        d = p - po
+        d -= melt300k.box[:, None] * np.round(d / melt300k.box[:, None])
+        out[precision] = (float(np.abs(d).max()), float(np.abs(v - vo).max()), T)
+        print("%s after 100 steps: max|dx| %.3e A, max|dv| %.3e A/fs, T %.6f (oracle %.6f)"
+              % (precision, out[precision][0], out[precision][1], T, eo["temperature"]), flush=True)
+    assert out["fp64"][0] <= 1e-8 and out["fp64"][2] == pytest.approx(eo["temperature"], rel=1e-10)
+    assert out["mixed"][0] <= 1e-4 and out["mixed"][2] == pytest.approx(eo["temperature"], rel=1e-5)
+
+
+def test_melt3M_bins_and_sampled_forces(ff):
+    """3,000,000 atoms at 0.85 g/cm^3: bins bit-exact, every bonded force, 2,000 sampled LJ
+    forces."""
+    O.set_threads(threads())
+    melt = build_melts(WORKLOADS["melt3M_mixed"], threads())[0]
+    s = system(ff, [melt], WORKLOADS["melt3M_mixed"], cell_div=0, lj_kernel=0, use_graph=True)
+    print("tuned (R, kernel) =", s.tuning(), flush=True)
+    check_bins(s, melt)
+    check_sampled_forces(ff, s, melt, 2000, 23)
+    s.close()
+
+
+def test_ensemble64_smallest_box(ff):
+    """The 64-box ensemble (about 4.3M atoms) in one launch sequence: every box's bins, and
+    the smallest box's forces, energies and first 100 steps against the oracle."""
+    O.set_threads(threads())
+    wl = WORKLOADS["ensemble64_mixed"]
+    melts = build_melts(wl, threads())
+    s = system(ff, melts, wl, cell_div=0, lj_kernel=0, use_graph=True)
+    print("tuned (R, kernel) =", s.tuning(), flush=True)
+    for b, m in enumerate(melts):
+        check_bins(s, m, b)
+    b = int(np.argmin([m.n_atoms for m in melts]))
+    m = melts[b]
+    off = sum(x.n_atoms for x in melts[:b])
+    f = s.forces()[:, off:off + m.n_atoms]
+    fo, eo = O.forces(ff, m.pos, m.types, m.box, m.chain_len)
+    print("smallest box %d (%d atoms): force error %.3e" % (b, m.n_atoms, rel_err(f - fo, fo)), flush=True)
+    assert rel_err(f - fo, fo) <= TOL
+    energy_close(s.energies()[b], eo)
+    s.step(100)
+    p, v = s.state()
+    p, v = p[:, off:off + m.n_atoms], v[:, off:off + m.n_atoms]
+    e100 = s.energies()
+    s.close()
+    po, vo, _, eo100 = O.run(ff, m.pos, m.vel, fo, m.types, m.box, m.chain_len, 100, dt=wl.dt_fs,
+                             tau=wl.tau_fs, T0=wl.T0[b])
+    d = p - po
+    d -= m.box[:, None] * np.round(d / m.box[:, None])
+    print("smallest box after 100 steps: max|dx| %.3e A, T %.6f (oracle %.6f)"
+          % (np.abs(d).max(), e100[b]["temperature"], eo100["temperature"]), flush=True)
+    assert np.abs(d).max() <= 1e-4
+    assert e100[b]["temperature"] == pytest.approx(eo100["temperature"], rel=1e-5)

@@ -71,3 +71,29 @@ def test_melt_clearance_and_determinism():
     i, j = pairs[:, 0], pairs[:, 1]
     nonlocal_ = (i // 300 != j // 300) | (np.abs(i - j) > 3)
     assert not nonlocal_.any()
+
+
+def test_tiled_melt_copies_the_small_melt():
+    """tiles^3 copies of a small melt: bonds intact across the copy faces, the large box holds
+    the same density, and every atom's nearest non-bonded neighbour is the one it had in the
+    small periodic box."""
+    from scipy.spatial import cKDTree
+
+    from pe_melt import box_length, make_melt, make_tiled_melt, unwrap_chains
+    small = make_melt(10, density=0.85, T=300.0, seed_melt=31, seed_vel=32)
+    big = make_tiled_melt(80, 2, density=0.85, T=300.0, seed_melt=31, seed_vel=32)
+    assert big.n_atoms == 8 * small.n_atoms
+    assert np.allclose(big.box, 2 * small.box) and big.box[0] == pytest.approx(box_length(80, 300, 0.85), rel=1e-12)
+    u = unwrap_chains(big.pos, big.box, 300).T.reshape(-1, 300, 3)
+    b = np.sqrt(np.sum(np.diff(u, axis=1) ** 2, axis=-1))
+    assert np.allclose(b, 1.53, atol=1e-9)
+    assert np.all((big.pos >= 0) & (big.pos < big.box[:, None]))
+
+    def nearest(m):
+        t = cKDTree(m.pos.T, boxsize=m.box)
+        d, _ = t.query(m.pos.T, k=2)
+        return np.sort(d[:, 1])
+    ds, db = nearest(small), nearest(big)
+    np.testing.assert_allclose(db[::8], ds, rtol=0, atol=1e-9)
+    # velocities are drawn for the whole system, not copied
+    assert not np.allclose(big.vel[:, :small.n_atoms], big.vel[:, small.n_atoms:2 * small.n_atoms])
