@@ -90,7 +90,7 @@ md_status validate(const md_forcefield* ff, const md_config* cfg, std::string* w
     if (!std::isfinite(cfg->T0[b])) { *why = "T0 must be finite"; return MD_ERR_ARG; }
     N += (int64_t)cfg->n_chains[b] * cfg->chain_len;
   }
-  if (N < 2 || N > kMaxAtoms) { *why = "total atoms must be in [2, 2^27]"; return MD_ERR_ARG; }
+  if (N < 2 || N > kMaxAtoms) { *why = "total atoms must be in [2, 2^25]"; return MD_ERR_ARG; }
   return MD_OK;
 }
 

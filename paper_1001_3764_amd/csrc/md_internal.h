@@ -32,7 +32,7 @@ constexpr float kInvFix2F = 8.8817841970012523e-16f;  // 2^-50
 __host__ __device__ inline int32_t tag_index(int32_t tag) { return tag >> 4; }
 __host__ __device__ inline int32_t tag_type(int32_t tag) { return (tag >> 3) & 1; }
 __host__ __device__ inline int32_t tag_cx(int32_t tag) { return tag & 7; }
-constexpr int64_t kMaxAtoms = (int64_t)1 << 27;
+constexpr int64_t kMaxAtoms = (int64_t)1 << 25;   // the LJ candidate list packs sorted index << 7
 
 struct BoxDev {
   double L[3], invL[3];   // edges and 1/L (computed on the host)

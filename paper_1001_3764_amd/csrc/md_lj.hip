@@ -130,7 +130,9 @@ __device__ __forceinline__ float r2_fix(float dx, float dy, float dz) {
 // (r2s >= 0, so integer order is float order), so that the caller sees a band pair
 // (bmax >= lo) at one integer max per pair and settles it.
 // Returns r2s.  BRANCHLESS evaluates the force for every lane and zeroes it outside.
-template <bool ENERGY, bool BRANCHLESS>
+// FOLD: f12 holds f12 / f6 and the caller multiplies the summed force by f6 (one type
+// pair: the force factor is then one FMA with an inline constant and no register copy).
+template <bool ENERGY, bool BRANCHLESS, bool FOLD = false>
 __device__ __forceinline__ float pair_fix(int dqx, int dqy, int dqz, bool keep, const Band& bd, float f12,
                                           float f6, float e12, float e6, float ecut, float& ax, float& ay,
                                           float& az, double& e, double& es, double& w, int32_t& bmax) {
@@ -141,7 +143,7 @@ __device__ __forceinline__ float pair_fix(int dqx, int dqy, int dqz, bool keep, 
     const float r2 = r2s * kInvFix2F;
     const float r2i = rcp_f(r2);
     const float r6 = r2i * r2i * r2i;
-    const float g = r6 * (f12 * r6 - f6);             // = F . r, kcal/mol
+    const float g = FOLD ? r6 * __builtin_fmaf(f12, r6, -1.0f) : r6 * (f12 * r6 - f6);   // F . r (/ f6)
     float ffs = g * r2i;
     if (BRANCHLESS) ffs = hit ? ffs : 0.0f;
     ax += ffs * dx;
@@ -152,7 +154,7 @@ __device__ __forceinline__ float pair_fix(int dqx, int dqy, int dqz, bool keep, 
       const float en = r6 * (e12 * r6 - e6);
       e += (double)en;
       es += (double)en - (double)ecut;
-      w += (double)g;
+      w += (double)(FOLD ? g * f6 : g);
     }
   }
   return r2s;
@@ -291,71 +293,65 @@ __global__ __launch_bounds__(kLjAtomBlock) void k_lj_atom(Views v, FFDev ff, LjP
 }
 
 // ---------------------------------------------------------------------------------
-// Cell tile: wave = one home cell.
-struct Piece {
-  int start, count;   // sorted-array range of consecutive cells of one stencil row
-  int ox0, cx0;       // x-offset of the first cell from the home cell, and its x index
-  int oy, oz;         // row offsets
-};
-constexpr int kMaxPieces = 2 * (2 * kTileMaxR + 1) * (2 * kTileMaxR + 1);
+// Cell tile: one wave per home cell.  The wave lists its (2R+1)^3 stencil once, as a flat
+// array of candidates in LDS (sorted-array index << 7 | stencil offset code), and streams
+// that list 64 lanes at a time against up to KMAX home atoms held wave-uniform.
+constexpr int kListCap = 1024;   // candidates a wave lists at a time
+constexpr int kMaxStencil = (2 * kTileMaxR + 1) * (2 * kTileMaxR + 1) * (2 * kTileMaxR + 1);
+static_assert(kMaxStencil <= 128, "stencil code must fit 7 bits");
 
-// Candidate t of a piece, moved into the home cell's frame (x-offset from its cell tag).
-template <bool FP64, typename PayT, typename Q>
-__device__ __forceinline__ void fetch_candidate(const PayT* __restrict__ pay, const Piece& pc, int t, const BoxDev& B,
-                                                Q ex, Q& jx, Q& jy, Q& jz, int32_t& jt) {
-  const PayT q = pay[t];
-  jt = pay_tag(q);
-  const int ox = pc.ox0 + ((tag_cx(jt) - pc.cx0) & 7);
-  if constexpr (FP64) {
-    jx = q.x + ox * B.edge[0];
-    jy = q.y + pc.oy * B.edge[1];
-    jz = q.z + pc.oz * B.edge[2];
-  } else {
-    jx = q.x + ox * ex;
-    jy = q.y + pc.oy * B.edge_q[1];
-    jz = q.z + pc.oz * B.edge_q[2];
+template <typename Q>
+struct Shift {
+  Q x, y, z;   // stencil offset (ox, oy, oz) times the cell edge, in the payload's units
+};
+
+__device__ __forceinline__ int wave_exclusive_scan(int x, int& total) {
+  const int ln = lane();
+  int s = x;
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(s, d);
+    if (ln >= d) s += y;
   }
+  total = __shfl(s, 63);
+  return s - x;
 }
 
-// Stencil rows of home cell lc -> contiguous pieces of the sorted arrays (a row that wraps
-// in x is split in two), written to pcs in lane order.  Returns their number (the same on
-// every lane).
-__device__ __forceinline__ int build_pieces(const Views& v, const BoxDev& B, int lc, bool wact, Piece* pcs) {
+// Writes entries [c0, c0 + kListCap) of home cell lc's candidate list to list[]; returns
+// the list's full length (the same on every lane).  Lane l lists stencil codes 2l and
+// 2l + 1 (x-neighbours, so consecutive entries are mostly consecutive in memory).
+__device__ __forceinline__ int fill_list(const Views& v, const BoxDev& B, int lc, int c0, uint32_t* list) {
   const int ln = lane();
-  const int R = v.R, W = 2 * R + 1;
+  const int R = v.R, W = 2 * R + 1, W3 = W * W * W;
   const int M0 = B.M[0], M1 = B.M[1], M2 = B.M[2];
   const int kx = lc % M0, ky = (lc / M0) % M1, kz = lc / (M0 * M1);
-  const int32_t* __restrict__ cs = v.cell_start;
-  Piece p1{0, 0, 0, 0, 0, 0}, p2{0, 0, 0, 0, 0, 0};
-  int has = 0;
-  if (wact && ln < W * W) {
-    const int oy = ln % W - R, oz = ln / W - R;
-    int ny = ky + oy;
-    ny += ny < 0 ? M1 : 0;
-    ny -= ny >= M1 ? M1 : 0;
-    int nz = kz + oz;
-    nz += nz < 0 ? M2 : 0;
-    nz -= nz >= M2 ? M2 : 0;
-    const int row = B.cell_off + M0 * (ny + M1 * nz);
-    const int xa = kx - R, xb = kx + R;
-    if (xa >= 0 && xb < M0) {
-      p1 = Piece{cs[row + xa], cs[row + xb + 1] - cs[row + xa], -R, xa, oy, oz};
-      has = 1;
-    } else if (xa < 0) {
-      p1 = Piece{cs[row + xa + M0], cs[row + M0] - cs[row + xa + M0], -R, xa + M0, oy, oz};
-      p2 = Piece{cs[row], cs[row + xb + 1] - cs[row], -kx, 0, oy, oz};
-      has = 2;
-    } else {
-      p1 = Piece{cs[row + xa], cs[row + M0] - cs[row + xa], -R, xa, oy, oz};
-      p2 = Piece{cs[row], cs[row + xb - M0 + 1] - cs[row], M0 - kx, 0, oy, oz};
-      has = 2;
+  int start[2], n[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int code = 2 * ln + h;
+    start[h] = 0;
+    n[h] = 0;
+    if (code < W3) {
+      int nx = kx + code % W - R, ny = ky + (code / W) % W - R, nz = kz + code / (W * W) - R;
+      nx += nx < 0 ? M0 : 0;
+      nx -= nx >= M0 ? M0 : 0;
+      ny += ny < 0 ? M1 : 0;
+      ny -= ny >= M1 ? M1 : 0;
+      nz += nz < 0 ? M2 : 0;
+      nz -= nz >= M2 ? M2 : 0;
+      const int c = B.cell_off + nx + M0 * (ny + M1 * nz);
+      start[h] = v.cell_start[c];
+      n[h] = v.cell_start[c + 1] - start[h];
     }
   }
-  const uint64_t m1 = __ballot(has >= 1), m2 = __ballot(has == 2);
-  const int idx = lanes_below(m1) + lanes_below(m2);
-  if (has >= 1) pcs[idx] = p1;
-  if (has == 2) pcs[idx + 1] = p2;
-  return __popcll(m1) + __popcll(m2);
+  int total;
+  int f = wave_exclusive_scan(n[0] + n[1], total);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int a1 = min(n[h], c0 + kListCap - f);
+    for (int a = max(0, c0 - f); a < a1; ++a) list[f + a - c0] = ((uint32_t)(start[h] + a) << 7) | (2 * ln + h);
+    f += n[h];
+  }
+  return total;
 }
 
 struct BandEnergy {
@@ -363,40 +359,60 @@ struct BandEnergy {
 };
 
 // Settles the cutoff-band pairs of one home group of a mixed tile wave, after its home
-// forces are stored.  First the recorded candidate steps are revisited and their band
-// pairs queued in (step, home, lane) order; each queued pair is then re-decided in FP64
-// and, when outside, taken back out of the stored force of its home (summed per home over
-// the lanes, applied by the lane that stored that home).  With more steps or pairs than
-// the slots hold (not expected in a melt) the whole candidate set of each home is walked
-// again instead.  LDS executes a wave's accesses in order and only this wave wrote its
-// slots, so no barrier is needed.  Out of line: this runs for about one group in 100, and
-// inline it would raise the register count of the pair loop.
+// forces are stored.  The recorded candidate steps (flat list positions) are revisited and
+// their band pairs queued in (step, home, lane) order, refilling the list where a step lies
+// in another chunk; each queued pair is then re-decided in FP64 and, when outside, taken
+// back out of the stored force of its home (summed per home over the lanes, applied by the
+// lane that stored that home).  With more steps or pairs than the slots hold (not
+// expected in a melt) every candidate of the group is walked again instead.  LDS executes
+// a wave's accesses in order and only this wave wrote its slots, so no barrier is needed.
+// `resident` is the chunk the list holds; it is updated.
 template <bool ENERGY, bool UNI>
 __device__ __forceinline__ BandEnergy settle_band_group(const Views& v, int chain_len, int excl, double rc2,
-                                                     const LjPair<float>& cf, const BoxDev& B, Band bd,
-                                                     const Piece* pcs, int np, const int2 (*steps)[2],
-                                                     int32_t* bq, const int4* __restrict__ pay, int hs, int g0,
-                                                     int kc, int nsteps) {
-  const int ln = lane(), half = ln >> 5, hl = ln & 31;
-  const int ex = B.edge_q[0];
+                                                        const LjPair<float>& cf, const BoxDev& B, Band bd, int lc,
+                                                        int total, uint32_t* list, int& resident,
+                                                        const Shift<int>* shifts, const int* steps, int32_t* bq,
+                                                        const int4* __restrict__ pay, int hs, int g0, int kc,
+                                                        int nsteps) {
+  const int ln = lane();
   float* f = static_cast<float*>(v.f_lj);
   double e = 0.0, es = 0.0, w = 0.0;
+  auto candidate = [&](int t, int cn, int& jx, int& jy, int& jz, int32_t& jt) -> bool {
+    jx = jy = jz = 0;
+    jt = 0;
+    if (t < cn) {
+      const uint32_t ent = list[t];
+      const int4 q = pay[ent >> 7];
+      const Shift<int> sh = shifts[ent & 127];
+      jt = pay_tag(q);
+      jx = q.x + sh.x;
+      jy = q.y + sh.y;
+      jz = q.z + sh.z;
+    }
+    return t < cn;
+  };
+  auto window = [&](int i, int32_t& hlo, uint32_t& hspan) {
+    const int32_t c0 = i - i % chain_len;
+    hlo = max(i - excl, c0);
+    hspan = (uint32_t)(min(i + excl, c0 + chain_len - 1) - hlo);
+  };
   int qn = 0;
   if (nsteps <= kBandSteps) {
     for (int s = 0; s < nsteps; ++s) {
-      const int2 po = steps[s][half];
-      Piece pc{0, 0, 0, 0, 0, 0};
-      if (po.x < np) pc = pcs[po.x];
-      const bool act = po.x < np && po.y + hl < pc.count;
-      int jx = 0, jy = 0, jz = 0;
-      int32_t jt = 0;
-      if (act) fetch_candidate<false>(pay, pc, pc.start + po.y + hl, B, ex, jx, jy, jz, jt);
+      const int fs = steps[s];
+      const int c0 = fs - fs % kListCap;
+      if (c0 != resident) {
+        fill_list(v, B, lc, c0, list);
+        resident = c0;
+      }
+      int jx, jy, jz;
+      int32_t jt;
+      const bool act = candidate(fs - c0 + ln, min(kListCap, total - c0), jx, jy, jz, jt);
       for (int k = 0; k < kc; ++k) {
         const int4 hq = pay[hs + g0 + k];
-        const int32_t i = tag_index(pay_tag(hq));
-        const int32_t c0 = i - i % chain_len;
-        const int32_t hlo = max(i - excl, c0);
-        const uint32_t hspan = (uint32_t)(min(i + excl, c0 + chain_len - 1) - hlo);
+        int32_t hlo;
+        uint32_t hspan;
+        window(tag_index(pay_tag(hq)), hlo, hspan);
         const bool keep = act && (uint32_t)(tag_index(jt) - hlo) > hspan;
         const bool qb = in_band(r2_fix((float)(hq.x - jx), (float)(hq.y - jy), (float)(hq.z - jz)), keep, bd);
         const uint64_t qm = __ballot(qb);
@@ -439,20 +455,24 @@ __device__ __forceinline__ BandEnergy settle_band_group(const Views& v, int chai
     for (int k = 0; k < kc; ++k) {
       const int4 hq = pay[hs + g0 + k];
       const int32_t i = tag_index(pay_tag(hq));
-      const int32_t c0 = i - i % chain_len;
-      const int32_t hlo = max(i - excl, c0);
-      const uint32_t hspan = (uint32_t)(min(i + excl, c0 + chain_len - 1) - hlo);
+      int32_t hlo;
+      uint32_t hspan;
+      window(i, hlo, hspan);
       float bx = 0.0f, by = 0.0f, bz = 0.0f;
-      for (int q = 0; q < np; ++q) {
-        const Piece pc = pcs[q];
-        for (int t = ln; t < pc.count; t += 64) {
+      for (int c0 = 0; c0 < total; c0 += kListCap) {
+        if (c0 != resident) {
+          fill_list(v, B, lc, c0, list);
+          resident = c0;
+        }
+        const int cn = min(kListCap, total - c0);
+        for (int t0 = 0; t0 < cn; t0 += 64) {
           int jx, jy, jz;
           int32_t jt;
-          fetch_candidate<false>(pay, pc, pc.start + t, B, ex, jx, jy, jz, jt);
+          const bool act = candidate(t0 + ln, cn, jx, jy, jz, jt);
           const int32_t jidx = tag_index(jt);
           const float r2s = r2_fix((float)(hq.x - jx), (float)(hq.y - jy), (float)(hq.z - jz));
           double d[3], r2;
-          if (in_band(r2s, (uint32_t)(jidx - hlo) > hspan, bd) &&
+          if (in_band(r2s, act && (uint32_t)(jidx - hlo) > hspan, bd) &&
               !inside_cutoff_f64(v.pos, v.N, B, i, jidx, rc2, d, r2)) {
             const int tt = UNI ? 0 : tag_type(pay_tag(hq)) * 2 + tag_type(jt);
             remove_band_pair<ENERGY>(d, r2, pick(cf.f12, tt), pick(cf.f6, tt), pick(cf.e12, tt),
@@ -475,19 +495,23 @@ __device__ __forceinline__ BandEnergy settle_band_group(const Views& v, int chai
   return BandEnergy{e, es, w};
 }
 
+// Occupancy targets (measured): the mixed form is held to 6 waves per SIMD (80 VGPRs; left
+// alone the compiler takes 82 and runs 5, and the few values it then spills sit outside the
+// pair loop: 8% faster); the FP64 form (K = 4) fits 8.
 template <bool FP64, bool ENERGY, bool UNI, int KMAX, bool BRANCHLESS>
-__global__ __launch_bounds__(64 * kTileWaves) void k_lj_tile(Views v, FFDev ff, LjPair<float> cf,
-                                                             LjPair<double> cd) {
+__global__ __launch_bounds__(64 * kTileWaves) __attribute__((amdgpu_waves_per_eu(FP64 ? 8 : 6)))
+void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
   using PayT = std::conditional_t<FP64, Pay64, int4>;
   using P = std::conditional_t<FP64, double, float>;
   using Q = std::conditional_t<FP64, double, int>;     // coordinate type
-  __shared__ Piece pieces[kTileWaves][kMaxPieces];
+  __shared__ uint32_t list[kTileWaves][kListCap];
+  __shared__ Shift<Q> shifts[kMaxStencil];
   __shared__ dd red[kTileWaves][3];
   __shared__ int32_t bq[kTileWaves][kBandQueue];   // queued band pairs: j << 4 | type_j << 3 | k
-  __shared__ int2 bsteps[kTileWaves][kBandSteps][2];   // (piece, offset) of each half at a band step
+  __shared__ int bsteps[kTileWaves][kBandSteps];    // flat list position of each band step
 
   const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
-  const int ln = lane(), half = ln >> 5, hl = ln & 31;
+  const int ln = lane();
   // Workgroups are dealt to the 8 XCDs round-robin; give each XCD a contiguous run of
   // home cells (a slab of the box) so its L2 holds one neighbourhood of the payload.
   const int per_xcd = (int)gridDim.x / kXcds;
@@ -500,7 +524,20 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_lj_tile(Views v, FFDev ff, 
   const int32_t* __restrict__ cs = v.cell_start;
   const PayT* __restrict__ pay = static_cast<const PayT*>(v.payload);
 
-  const int np = build_pieces(v, B, lc, wact, pieces[wave]);
+  // stencil offsets in the payload's units (the same for every wave of the block)
+  {
+    const int R = v.R, W = 2 * R + 1;
+    const int code = (int)threadIdx.x;
+    if (code < W * W * W) {
+      const int ox = code % W - R, oy = (code / W) % W - R, oz = code / (W * W) - R;
+      if constexpr (FP64)
+        shifts[code] = Shift<Q>{ox * B.edge[0], oy * B.edge[1], oz * B.edge[2]};
+      else
+        shifts[code] = Shift<Q>{ox * B.edge_q[0], oy * B.edge_q[1], oz * B.edge_q[2]};
+    }
+  }
+  int total = 0, resident = 0;
+  if (wact) total = __builtin_amdgcn_readfirstlane(fill_list(v, B, lc, 0, list[wave]));
   __syncthreads();
 
   double e = 0.0, es = 0.0, w = 0.0;
@@ -508,7 +545,9 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_lj_tile(Views v, FFDev ff, 
     const int hs = __builtin_amdgcn_readfirstlane(cs[B.cell_off + lc]);
     const int hn = __builtin_amdgcn_readfirstlane(cs[B.cell_off + lc + 1]) - hs;
     const Band bd = make_band(ff.rc2);
-    const Q ex = FP64 ? (Q)0 : (Q)B.edge_q[0];
+    // one type pair (mixed): forces are summed divided by f6 (see pair_fix)
+    const float f12_fold = cf.f12[0] / cf.f6[0];
+    const float fscale = UNI ? kInvFixF * cf.f6[0] : kInvFixF;
     for (int g0 = 0; g0 < hn; g0 += KMAX) {
       const int kc = min(KMAX, hn - g0);
       Q hx[KMAX], hy[KMAX], hz[KMAX];
@@ -544,49 +583,53 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_lj_tile(Views v, FFDev ff, 
           hti[k] = 0;
         }
       }
-      // two candidate streams, one per 32-lane half: pieces half, half+2, half+4, ...
       int nsteps = 0;       // candidate steps with a band pair (wave-uniform)
       int32_t bmax = 0;     // bits of the largest r2s counted since the last band check
-      int p = half, o = 0;
-      while (true) {
-        const bool hv = p < np;
-        if (__ballot(hv) == 0) break;
-        Piece pc{0, 0, 0, 0, 0, 0};
-        if (hv) pc = pieces[wave][p];
-        const bool act = hv && (o + hl < pc.count);
-        Q jx = (Q)0, jy = (Q)0, jz = (Q)0;
-        int32_t jt = 0;
-        if (act) fetch_candidate<FP64>(pay, pc, pc.start + o + hl, B, ex, jx, jy, jz, jt);
-        const int32_t jidx = tag_index(jt);
-        const int jtype = tag_type(jt);
+      for (int c0 = 0; c0 < total; c0 += kListCap) {
+        if (c0 != resident) {
+          fill_list(v, B, lc, c0, list[wave]);
+          resident = c0;
+        }
+        const int cn = min(kListCap, total - c0);
+        for (int t0 = 0; t0 < cn; t0 += 64) {
+          const bool act = t0 + ln < cn;
+          Q jx = (Q)0, jy = (Q)0, jz = (Q)0;
+          int32_t jt = 0;
+          if (act) {
+            const uint32_t ent = list[wave][t0 + ln];
+            const PayT q = pay[ent >> 7];
+            const Shift<Q> sh = shifts[ent & 127];
+            jt = pay_tag(q);
+            jx = q.x + sh.x;
+            jy = q.y + sh.y;
+            jz = q.z + sh.z;
+          }
+          const int32_t jidx = tag_index(jt);
+          const int jtype = tag_type(jt);
 #pragma unroll
-        for (int k = 0; k < KMAX; ++k) {
-          if (k < kc) {
-            const bool keep = act && (uint32_t)(jidx - lo[k]) > span[k];
-            const int tt = UNI ? 0 : hti[k] * 2 + jtype;
-            if constexpr (FP64)
-              pair_f64<ENERGY>(hx[k] - jx, hy[k] - jy, hz[k] - jz, keep, ff.rc2, pick(cd.f12, tt),
-                               pick(cd.f6, tt), pick(cd.e12, tt), pick(cd.e6, tt), pick(cd.ecut, tt), ax[k],
-                               ay[k], az[k], e, es, w);
-            else {
-              pair_fix<ENERGY, BRANCHLESS>(hx[k] - jx, hy[k] - jy, hz[k] - jz, keep, bd, pick(cf.f12, tt),
-                                           pick(cf.f6, tt), pick(cf.e12, tt), pick(cf.e6, tt), pick(cf.ecut, tt),
-                                           ax[k], ay[k], az[k], e, es, w, bmax);
+          for (int k = 0; k < KMAX; ++k) {
+            if (k < kc) {
+              const bool keep = act && (uint32_t)(jidx - lo[k]) > span[k];
+              const int tt = UNI ? 0 : hti[k] * 2 + jtype;
+              if constexpr (FP64)
+                pair_f64<ENERGY>(hx[k] - jx, hy[k] - jy, hz[k] - jz, keep, ff.rc2, pick(cd.f12, tt),
+                                 pick(cd.f6, tt), pick(cd.e12, tt), pick(cd.e6, tt), pick(cd.ecut, tt), ax[k],
+                                 ay[k], az[k], e, es, w);
+              else
+                pair_fix<ENERGY, BRANCHLESS, UNI>(hx[k] - jx, hy[k] - jy, hz[k] - jz, keep, bd,
+                                                  UNI ? f12_fold : pick(cf.f12, tt), pick(cf.f6, tt),
+                                                  pick(cf.e12, tt), pick(cf.e6, tt), pick(cf.ecut, tt), ax[k],
+                                                  ay[k], az[k], e, es, w, bmax);
             }
           }
-        }
-        if constexpr (!FP64) {
-          // rare: a lane counted a pair in the cutoff band; note where both halves were
-          if (__builtin_amdgcn_ballot_w64(bmax >= __float_as_int(bd.lo)) != 0) {
-            bmax = 0;
-            if (nsteps < kBandSteps && hl == 0) bsteps[wave][nsteps][half] = make_int2(p, o);
-            ++nsteps;
+          if constexpr (!FP64) {
+            // rare: a lane counted a pair in the cutoff band; note the step
+            if (__builtin_amdgcn_ballot_w64(bmax >= __float_as_int(bd.lo)) != 0) {
+              bmax = 0;
+              if (nsteps < kBandSteps && ln == 0) bsteps[wave][nsteps] = c0 + t0;
+              ++nsteps;
+            }
           }
-        }
-        o += 32;
-        if (hv && o >= pc.count) {
-          p += 2;
-          o = 0;
         }
       }
       // sum each home atom's partial forces over the 64 lanes (fixed butterfly order)
@@ -601,9 +644,9 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_lj_tile(Views v, FFDev ff, 
             sz += __shfl_xor(sz, off);
           }
           if constexpr (!FP64) {
-            sx *= kInvFixF;
-            sy *= kInvFixF;
-            sz *= kInvFixF;
+            sx *= fscale;
+            sy *= fscale;
+            sz *= fscale;
           }
           if (ln == k) {
             const int32_t i = tag_index(pay_tag(pay[hs + g0 + k]));
@@ -615,9 +658,9 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_lj_tile(Views v, FFDev ff, 
       }
       if constexpr (!FP64) {
         if (nsteps > 0) {
-          const BandEnergy be = settle_band_group<ENERGY, UNI>(v, ff.chain_len, ff.excl, ff.rc2, cf, B, bd,
-                                                               pieces[wave], np, bsteps[wave], bq[wave], pay, hs,
-                                                               g0, kc, nsteps);
+          const BandEnergy be = settle_band_group<ENERGY, UNI>(v, ff.chain_len, ff.excl, ff.rc2, cf, B, bd, lc,
+                                                               total, list[wave], resident, shifts, bsteps[wave],
+                                                               bq[wave], pay, hs, g0, kc, nsteps);
           if (ENERGY) {
             e += be.e;
             es += be.es;
