@@ -82,10 +82,10 @@ def measured_traffic(kernel_name):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(ff, melt, budget_s=12.0, max_steps=20):
+def cpu_baseline(ff, melt, budget_s=12.0, max_steps=20, threads=None):
     import numpy as np
     import oracle as O
-    threads = O.set_threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+    threads = O.set_threads(threads or int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
     f0, _ = O.forces(ff, melt.pos, melt.types, melt.box, melt.chain_len)
     p, v, f = melt.pos, melt.vel, f0
     steps = 0
@@ -241,11 +241,14 @@ def main():
                  "graph": False}
         log("fp64: %.3f ms/step, %.3e atom-steps/s" % (plain["ms_per_step"], v64))
 
-    cpu = None
+    cpu = cpu1 = None
     if not args.no_cpu_baseline:
         try:
             cpu = cpu_baseline(ff, melt)
             log("cpu oracle: %.3e atom-steps/s on %d threads" % (cpu["value"], cpu["cores"]))
+            # one core: the kind of baseline the paper compares against (single-core CPU MD)
+            cpu1 = cpu_baseline(ff, melt, budget_s=4.0, max_steps=1, threads=1)
+            log("cpu oracle, 1 thread: %.3e atom-steps/s" % cpu1["value"])
         except Exception as exc:
             log("cpu baseline failed: %r" % (exc,))
 
@@ -267,6 +270,7 @@ def main():
         "final_temperature_K": e_end["temperature"],
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "cpu_baseline_1thread": cpu1,
     }
     print(json.dumps(out), flush=True)
 
@@ -370,6 +374,37 @@ def run_other_workload(args):
         err = float(np.max(np.sqrt(np.sum((f - fo) ** 2, axis=0)) / np.maximum(fn, np.sqrt(np.mean(fn ** 2)))))
         extra["smallest_box"] = {"box": b, "atoms": m.n_atoms, "force_max_rel_err_vs_oracle": err}
         log("smallest box %d (%d atoms): force error %.3e" % (b, m.n_atoms, err))
+
+    if wl.name == "ensemble64_mixed":
+        # the same 64 boxes one context (one launch sequence) per box, stepped in turn: separates
+        # the effect of batching from that of precision
+        per_box = {}
+        box_steps = 100
+        for precision, graph in (("mixed", not args.no_graph), ("fp64", False)):
+            ctxs = []
+            off = 0
+            for m in melts:
+                sl = slice(off, off + m.n_atoms)
+                ctxs.append(MDSystem(ff, [m.n_chains], m.box[None, :], [wl.T0[len(ctxs)]], pos[:, sl], vel[:, sl],
+                                     types[sl], chain_len=wl.chain_len, dt=wl.dt_fs, tau=wl.tau_fs,
+                                     precision=precision, cell_div=R, lj_kernel=kern, use_graph=graph, device=dev))
+                off += m.n_atoms
+            for c in ctxs:
+                c.step(5)
+            torch.cuda.synchronize(dev)
+            a = time.perf_counter()
+            for c in ctxs:
+                c.step(box_steps)
+            torch.cuda.synchronize(dev)
+            b_ = time.perf_counter()
+            for c in ctxs:
+                c.close()
+            per_box["%s_per_box%s" % (precision, "_graph" if graph else "")] = {
+                "value": N * box_steps / (b_ - a), "unit": "atom-steps/s", "steps": box_steps,
+                "ms_per_step_all_boxes": 1e3 * (b_ - a) / box_steps}
+            log("%s per box (%s): %.3e atom-steps/s" % (precision, "graph" if graph else "no graph",
+                                                        N * box_steps / (b_ - a)))
+        extra["per_box_forms"] = per_box
 
     plain = None
     if not args.no_fp64:
