@@ -112,6 +112,7 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-nlist", action="store_true", help="skip the neighbour-list form")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first copy a device buffer of this many MiB (HBM counter calibration)")
     ap.add_argument("--workload", default="melt300k_mixed",
@@ -176,10 +177,44 @@ def main():
     phases = s.step_timed(n_prof)
     phase_avg = {k: v / n_prof for k, v in phases.items()}
     start_prof, _ = s.bins()
-    pos_prof, _ = s.state()
+    pos_prof, vel_prof = s.state()
     f_end = s.forces()
     f_end_lj = s.forces(lj_only=True)
     s.close()
+
+    # ---- the paper's force path beside it: Verlet lists (skin 1 A) rebuilt every 10 steps,
+    # from the state the timed run ended in (mixed, graph-replayed) ----
+    nlist = None
+    if not args.no_nlist:
+        try:
+            sn = MDSystem(ff, [melt.n_chains], melt.box[None, :], [wl.T0[0]], pos_prof, vel_prof, melt.types,
+                          chain_len=wl.chain_len, dt=wl.dt_fs, tau=wl.tau_fs, precision="mixed", cell_div=0,
+                          use_graph=not args.no_graph, device=dev, nl_skin=1.0, nl_every=10)
+            Rn, _ = sn.tuning()
+            fn_lj = sn.forces(lj_only=True)
+            sn.step(50)
+            torch.cuda.synchronize(dev)
+            a = time.perf_counter()
+            n_nl = min(args.steps, 2000)
+            sn.step(n_nl)
+            torch.cuda.synchronize(dev)
+            b_ = time.perf_counter()
+            ph = {k: v / 100 for k, v in sn.step_timed(100).items()}
+            status = "ok"
+            try:
+                sn.energies()
+            except Exception as exc:
+                status = str(exc)
+            sn.close()
+            nlist = {"value": N * n_nl / (b_ - a), "unit": "atom-steps/s", "steps": n_nl,
+                     "ms_per_step": 1e3 * (b_ - a) / n_nl, "skin_A": 1.0, "rebuild_every": 10, "cell_div": Rn,
+                     "phases_ms_avg": {k: round(v, 5) for k, v in ph.items()}, "status": status,
+                     "lj_force_max_diff_vs_cell_path_over_frms": float(
+                         np.max(np.sqrt(np.sum((fn_lj - f_end_lj) ** 2, axis=0)))
+                         / np.sqrt(np.mean(np.sum(f_end_lj ** 2, axis=0))))}
+            log("nlist: %.3f ms/step, %.3e atom-steps/s (%s)" % (nlist["ms_per_step"], nlist["value"], status))
+        except Exception as exc:
+            log("nlist run failed: %r" % (exc,))
 
     cand, pairs = candidate_and_pair_counts(pos_prof, melt.box, start_prof, M, R, ff["rc"], melt.n_chains,
                                             melt.chain_len)
@@ -271,6 +306,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "cpu_baseline_1thread": cpu1,
+        "nlist_form": nlist,
     }
     print(json.dumps(out), flush=True)
 

@@ -51,7 +51,10 @@ typedef enum {
   MD_ERR_NONFINITE = -3,      /* a coordinate or force became NaN or infinite (device) */
   MD_ERR_WORKSPACE = -4,      /* workspace smaller than md_workspace_bytes, or misaligned */
   MD_ERR_HIP = -6,            /* a HIP runtime call failed; md_last_error has the text */
-  MD_ERR_STATE = -7           /* the context is in an error state; re-initialise it */
+  MD_ERR_STATE = -7,          /* the context is in an error state; re-initialise it */
+  MD_ERR_NLIST = -8           /* neighbour-list mode (device): an atom moved more than half the
+                                 skin since the last list build, or an atom had more list
+                                 neighbours than the list holds; pairs may have been missed */
 } md_status;
 
 typedef enum {
@@ -66,8 +69,10 @@ typedef enum {
   MD_LJ_ATOM = 1,       /* one lane per home atom walking the neighbouring cells */
   MD_LJ_CELLTILE = 2,   /* one wavefront per home cell: home atoms wave-uniform, candidate
                            atoms across the lanes */
-  MD_LJ_CELLTILE_NB = 3 /* as MD_LJ_CELLTILE, with the pair force evaluated on every lane and
-                           zeroed outside the cutoff instead of branching (mixed precision) */
+  MD_LJ_CELLTILE_NB = 3, /* as MD_LJ_CELLTILE, with the pair force evaluated on every lane and
+                            zeroed outside the cutoff instead of branching (mixed precision) */
+  MD_LJ_NLIST = 4        /* reported by md_tuning in neighbour-list mode (nl_skin > 0): one lane
+                            per atom walking its Verlet list; not a valid lj_kernel request */
 } md_lj_kernel;
 
 /* Force field (Table I, Eqs. 2-6).  Types: 0 = CH2 (C_32), 1 = CH3 (C_33).  LJ pair
@@ -97,8 +102,15 @@ typedef struct {
   int32_t cell_div;           /* R: cells of edge >= rc / R, (2R+1)^3 cells visited;
                                  1 = the paper's grid (edge >= cutoff), 2 = half cells;
                                  0 = chosen by the autotuner at init */
-  int32_t lj_kernel;          /* md_lj_kernel */
+  int32_t lj_kernel;          /* md_lj_kernel (1..3, or 0 for the autotuner) */
   int32_t use_graph;          /* 1: md_step replays a captured hipGraph of the step */
+  double nl_skin;             /* > 0: neighbour-list mode.  A Verlet list of the pairs closer
+                                 than rc + nl_skin (A) is built from the bins, and the bins and
+                                 the list are rebuilt every nl_every steps instead of every step
+                                 (the paper's force path, Sections 3.1-3.2).  Every step checks
+                                 that no atom moved more than nl_skin / 2 since the build
+                                 (MD_ERR_NLIST otherwise).  0: forces from the cells every step */
+  int32_t nl_every;           /* steps between list builds, >= 1 (neighbour-list mode only) */
 } md_config;
 
 /* Per-box results of the most recent energy evaluation. */
@@ -133,7 +145,8 @@ md_status md_init_system(const md_forcefield* ff, const md_config* cfg, double* 
                          md_ctx** out);
 
 /* Wrap positions into their box, recompute cell indices and rebuild the cell lists
-   and the sorted coordinate payload (Section 3.1). */
+   and the sorted coordinate payload (Section 3.1); in neighbour-list mode also
+   rebuild the list. */
 md_status md_rebuild_bins(md_ctx* ctx);
 
 /* Forces at the positions of the last bin rebuild: LJ (Section 3.2) plus bonded
@@ -142,7 +155,9 @@ md_status md_rebuild_bins(md_ctx* ctx);
 md_status md_compute_forces(md_ctx* ctx, int32_t with_energy);
 
 /* Advance every box by n_steps (>= 0) velocity-Verlet steps with the bins rebuilt
-   every step; energies are evaluated on the last step.  Enqueues only. */
+   every step (in neighbour-list mode: every nl_every steps, counted from the last
+   build, together with the list); energies are evaluated on the last step.  Enqueues
+   only. */
 md_status md_step(md_ctx* ctx, int32_t n_steps);
 
 /* Phases timed by md_step_timed. */
@@ -154,8 +169,12 @@ enum {
   MD_PHASE_LJ = 4,             /* Lennard-Jones forces */
   MD_PHASE_BONDED = 5,         /* bonded forces, total force, second half kick */
   MD_PHASE_REDUCE = 6,         /* per-box sums and the thermostat factor */
-  MD_N_PHASES = 7
+  MD_PHASE_NLIST = 7,          /* neighbour-list build (neighbour-list mode, build steps only) */
+  MD_N_PHASES = 8
 };
+/* In neighbour-list mode MD_PHASE_INTEGRATE_BIN covers the update, the displacement
+   check and the payload refresh on the steps between builds, and the scan, scatter,
+   rank and list phases are empty on those steps. */
 
 /* Same as md_step but launched without the graph and with a pair of HIP events
    around every phase on the context's stream; adds each phase's summed duration in

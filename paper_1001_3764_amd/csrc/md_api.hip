@@ -34,8 +34,12 @@ struct md_ctx {
   size_t ws_bytes = 0;
   hipStream_t stream = nullptr;
   hipStream_t cap = nullptr;
-  hipGraph_t graph[2] = {nullptr, nullptr};
-  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  // graphs: [energy] for the cell path; [2 * build + energy] in neighbour-list mode
+  hipGraph_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipGraphExec_t exec[4] = {nullptr, nullptr, nullptr, nullptr};
+  double nl_skin = 0.0;      // > 0: neighbour-list mode
+  int nl_every = 1;
+  int since_build = 0;       // steps since the last list build
   int64_t step = 0;
   bool failed = false;
   std::string last_error;
@@ -82,6 +86,9 @@ md_status validate(const md_forcefield* ff, const md_config* cfg, std::string* w
   if (cfg->precision != MD_PREC_FP64 && cfg->precision != MD_PREC_MIXED) { *why = "bad precision"; return MD_ERR_ARG; }
   if (cfg->cell_div < 0 || cfg->cell_div > 3) { *why = "cell_div must be 0..3"; return MD_ERR_ARG; }
   if (cfg->lj_kernel < 0 || cfg->lj_kernel > 3) { *why = "lj_kernel must be 0..3"; return MD_ERR_ARG; }
+  if (!(cfg->nl_skin >= 0.0) || !std::isfinite(cfg->nl_skin)) { *why = "nl_skin must be >= 0"; return MD_ERR_ARG; }
+  if (cfg->nl_skin > 0.0 && cfg->nl_every < 1) { *why = "nl_every must be >= 1"; return MD_ERR_ARG; }
+  if (cfg->nl_skin > 0.0 && cfg->cell_div > kTileMaxR) { *why = "neighbour lists need cell_div <= 2"; return MD_ERR_ARG; }
   int64_t N = 0;
   for (int b = 0; b < cfg->n_boxes; ++b) {
     if (cfg->n_chains[b] < 1) { *why = "every box needs at least one chain"; return MD_ERR_ARG; }
@@ -96,6 +103,12 @@ md_status validate(const md_forcefield* ff, const md_config* cfg, std::string* w
 
 int cells_per_dim(double L, int R, double rc) { return (int)std::floor(L * R / rc); }
 
+// Distance the cell stencil must cover: the cutoff, or in neighbour-list mode the list
+// radius rc + skin (cells of edge >= (rc + skin) / R).
+double cell_reach(const md_forcefield* ff, const md_config* cfg) {
+  return ff->rc + (cfg->nl_skin > 0.0 ? cfg->nl_skin : 0.0);
+}
+
 constexpr int64_t kMaxScanTiles = (int64_t)kScanBlock * 8;   // k_scan_top: 8 tiles per thread
 
 bool grid_ok(const md_forcefield* ff, const md_config* cfg, int R) {
@@ -103,7 +116,7 @@ bool grid_ok(const md_forcefield* ff, const md_config* cfg, int R) {
   for (int b = 0; b < cfg->n_boxes; ++b) {
     int64_t nc = 1;
     for (int d = 0; d < 3; ++d) {
-      const int M = cells_per_dim(cfg->box[3 * b + d], R, ff->rc);
+      const int M = cells_per_dim(cfg->box[3 * b + d], R, cell_reach(ff, cfg));
       if (M < 2 * R + 1) return false;
       nc *= M;
     }
@@ -115,22 +128,41 @@ bool grid_ok(const md_forcefield* ff, const md_config* cfg, int R) {
 struct Plan {
   int64_t N = 0, C = 0;
   int32_t n_boxes = 0, n_atom_blocks = 0, n_lj_blocks = 0, n_tiles = 0;
+  int32_t n_cell_blocks = 0, nl_cap = 0;   // neighbour-list mode
+  int64_t nl_entries = 0;
   int prec = 0;
   std::vector<BoxDev> boxes;
 };
+
+// List entries per atom: the pairs within rc + skin of the densest box, with room for
+// fluctuations (a list that fills up is reported as MD_ERR_NLIST).
+int32_t nl_capacity(const md_forcefield* ff, const md_config* cfg) {
+  double rho = 0.0;
+  for (int b = 0; b < cfg->n_boxes; ++b)
+    rho = std::max(rho, (double)cfg->n_chains[b] * cfg->chain_len /
+                            (cfg->box[3 * b] * cfg->box[3 * b + 1] * cfg->box[3 * b + 2]));
+  const double rl = ff->rc + cfg->nl_skin;
+  const double mean = 4.0 / 3.0 * M_PI * rl * rl * rl * rho;
+  return (int32_t)((1.5 * mean + 64.0 + 15.0) / 16.0) * 16;
+}
 
 Plan make_plan(const md_forcefield* ff, const md_config* cfg, int R, int kernel) {
   Plan p;
   p.n_boxes = cfg->n_boxes;
   p.prec = cfg->precision;
-  int64_t atom = 0, cell = 0, blk = 0, lblk = 0;
+  const bool nl = cfg->nl_skin > 0.0;
+  if (nl) {
+    kernel = MD_LJ_NLIST;
+    p.nl_cap = nl_capacity(ff, cfg);
+  }
+  int64_t atom = 0, cell = 0, blk = 0, lblk = 0, cblk = 0, nle = 0;
   for (int b = 0; b < cfg->n_boxes; ++b) {
     BoxDev B{};
     const int64_t n = (int64_t)cfg->n_chains[b] * cfg->chain_len;
     int64_t nc = 1;
     for (int d = 0; d < 3; ++d) {
       const double L = cfg->box[3 * b + d];
-      const int M = cells_per_dim(L, R, ff->rc);
+      const int M = cells_per_dim(L, R, cell_reach(ff, cfg));
       B.L[d] = L;
       B.invL[d] = 1.0 / L;
       B.M[d] = M;
@@ -145,14 +177,22 @@ Plan make_plan(const md_forcefield* ff, const md_config* cfg, int R, int kernel)
     B.n_cells = (int32_t)nc;
     B.blk_off = (int32_t)blk;
     B.lj_blk_off = (int32_t)lblk;
+    B.cell_blk_off = (int32_t)cblk;
+    B.nl_off = nle;
     B.T0 = cfg->T0[b];
     B.dof = (double)(3 * n - 3);
     atom += n;
     cell += nc;
     blk += (n + kAtomBlock - 1) / kAtomBlock;
     lblk += lj_blocks_for_box(kernel, n, nc);
+    if (nl) {
+      cblk += (nc + kTileWaves - 1) / kTileWaves;
+      nle += (n + 63) / 64 * 64 * (int64_t)p.nl_cap;
+    }
     p.boxes.push_back(B);
   }
+  p.n_cell_blocks = (int32_t)cblk;
+  p.nl_entries = nle;
   p.N = atom;
   p.C = cell;
   p.n_atom_blocks = (int32_t)blk;
@@ -196,6 +236,16 @@ size_t carve(const Plan& p, char* base, Views* v) {
   t.lambda = (double*)take(8 * (size_t)p.n_boxes);
   t.energy = (double*)take(64 * (size_t)p.n_boxes);
   t.err = (int32_t*)take(4);
+  if (p.nl_cap) {
+    t.nl_cap = p.nl_cap;
+    t.n_cell_blocks = p.n_cell_blocks;
+    t.cell_blk_box = (const int32_t*)take(4 * (size_t)p.n_cell_blocks);
+    t.nl_list = (uint32_t*)take(4 * (size_t)p.nl_entries);
+    t.nl_count = (int32_t*)take(4 * (size_t)p.N);
+    t.x_build = (double*)take(24 * (size_t)p.N);
+    t.slot_of = (int32_t*)take(4 * (size_t)p.N);
+    t.pay_cur = take(psz * (size_t)p.N);
+  }
   if (v) *v = t;
   return off;
 }
@@ -252,12 +302,19 @@ md_status configure(md_ctx* c, const md_config* cfg, int R, int kernel) {
   v.pos = c->pos;
   v.vel = c->vel;
   v.type = c->type;
-  std::vector<int32_t> bb(p.n_atom_blocks), lb(p.n_lj_blocks);
+  std::vector<int32_t> bb(p.n_atom_blocks), lb(p.n_lj_blocks), cb(p.n_cell_blocks);
   for (int b = 0; b < p.n_boxes; ++b) {
     const int32_t e1 = b + 1 < p.n_boxes ? p.boxes[b + 1].blk_off : p.n_atom_blocks;
     for (int32_t k = p.boxes[b].blk_off; k < e1; ++k) bb[k] = b;
     const int32_t e2 = b + 1 < p.n_boxes ? p.boxes[b + 1].lj_blk_off : p.n_lj_blocks;
     for (int32_t k = p.boxes[b].lj_blk_off; k < e2; ++k) lb[k] = b;
+    const int32_t e3 = b + 1 < p.n_boxes ? p.boxes[b + 1].cell_blk_off : p.n_cell_blocks;
+    for (int32_t k = p.boxes[b].cell_blk_off; k < e3; ++k) cb[k] = b;
+  }
+  if (p.nl_cap) {
+    const double rl = c->ff.rc + cfg->nl_skin;
+    v.nl_rl2 = rl * rl;
+    v.nl_half_skin2 = 0.25 * cfg->nl_skin * cfg->nl_skin;
   }
   md_status st;
   // pageable sources: hipMemcpy (synchronous) so the host vectors may go away
@@ -271,6 +328,10 @@ md_status configure(md_ctx* c, const md_config* cfg, int R, int kernel) {
   if ((st = hip_check(c, hipMemcpy((void*)v.lj_blk_box, lb.data(), 4 * lb.size(), hipMemcpyHostToDevice),
                       "upload LJ block table")))
     return st;
+  if (p.nl_cap &&
+      (st = hip_check(c, hipMemcpy((void*)v.cell_blk_box, cb.data(), 4 * cb.size(), hipMemcpyHostToDevice),
+                      "upload list build block table")))
+    return st;
   launch_fill_i32(v.cnt, p.C, 0, c->stream);
   launch_fill_i32(v.err, 1, 0, c->stream);
   launch_fill_f64(v.lambda, p.n_boxes, 1.0, c->stream);
@@ -279,32 +340,52 @@ md_status configure(md_ctx* c, const md_config* cfg, int R, int kernel) {
   c->v = v;
   c->hboxes = p.boxes;
   c->R = R;
-  c->lj_kernel = kernel;
+  c->lj_kernel = p.nl_cap ? MD_LJ_NLIST : kernel;
+  c->since_build = 0;
   return MD_OK;
 }
 
+bool nl_mode(const md_ctx* c) { return c->v.nl_cap > 0; }
+
+// Bins (and, in neighbour-list mode, the list) from the current positions.
 void enqueue_rebuild(md_ctx* c, hipStream_t s, bool kick) {
   const bool fp32 = c->prec == MD_PREC_MIXED;
   launch_bin_count(c->v, kick, c->dt, c->ffd, fp32, s);
   launch_scan(c->v, s);
   launch_scatter(c->v, s);
   launch_rank_payload(c->v, fp32, s);
+  if (nl_mode(c)) launch_nl_build(c->v, c->ffd, fp32, s);
 }
 
-void enqueue_forces(md_ctx* c, hipStream_t s, bool kick, bool energy) {
+// build_step: the payload of the last rebuild is current (neighbour-list mode).
+void enqueue_forces(md_ctx* c, hipStream_t s, bool kick, bool energy, bool build_step = true) {
   const bool fp32 = c->prec == MD_PREC_MIXED;
-  launch_lj(c->v, c->ffd, fp32, c->lj_kernel, energy, s);
+  if (nl_mode(c))
+    launch_lj_nl(c->v, c->ffd, fp32, energy, build_step, s);
+  else
+    launch_lj(c->v, c->ffd, fp32, c->lj_kernel, energy, s);
   launch_bonded(c->v, c->ffd, fp32, kick, energy, c->dt, s);
 }
 
-void enqueue_step(md_ctx* c, hipStream_t s, bool energy) {
-  enqueue_rebuild(c, s, true);
-  enqueue_forces(c, s, true, energy);
+// One step.  build: rebuild bins and list (always true for the cell path).
+void enqueue_step(md_ctx* c, hipStream_t s, bool energy, bool build = true) {
+  if (nl_mode(c) && !build) {
+    launch_nl_integrate(c->v, c->dt, c->ffd, c->prec == MD_PREC_MIXED, s);
+    enqueue_forces(c, s, true, energy, false);
+  } else {
+    enqueue_rebuild(c, s, true);
+    enqueue_forces(c, s, true, energy, true);
+  }
   launch_reduce(c->v, energy, true, c->dt, c->tau, s);
 }
 
+// Whether the next step rebuilds bins and list (a list serves nl_every force evaluations).
+bool next_step_builds(const md_ctx* c) { return !nl_mode(c) || c->since_build + 1 >= c->nl_every; }
+
+void advance_build_counter(md_ctx* c, bool built) { c->since_build = built ? 0 : c->since_build + 1; }
+
 void destroy_graphs(md_ctx* c) {
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < 4; ++k) {
     if (c->exec[k]) (void)hipGraphExecDestroy(c->exec[k]);
     if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
     c->exec[k] = nullptr;
@@ -317,10 +398,10 @@ md_status capture_graphs(md_ctx* c) {
   md_status st;
   if (!c->cap && (st = hip_check(c, hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking), "capture stream")))
     return st;
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < (nl_mode(c) ? 4 : 2); ++k) {
     if ((st = hip_check(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal), "begin capture")))
       return st;
-    enqueue_step(c, c->cap, k == 1);
+    enqueue_step(c, c->cap, (k & 1) != 0, !nl_mode(c) || k >= 2);
     hipError_t le = hipGetLastError();
     hipError_t e = hipStreamEndCapture(c->cap, &c->graph[k]);
     if ((st = hip_check(c, le, "launch during capture"))) return st;
@@ -339,7 +420,10 @@ md_status autotune(md_ctx* c, const md_config* cfg, int* bestR, int* bestK) {
   else
     for (int R = 1; R <= 2; ++R)
       if (grid_ok(&c->ff, cfg, R)) Rs.push_back(R);
-  if (cfg->lj_kernel) Ks.push_back(cfg->lj_kernel);
+  if (cfg->nl_skin > 0.0) {
+    Ks.push_back(MD_LJ_NLIST);
+    Rs.erase(std::remove_if(Rs.begin(), Rs.end(), [](int R) { return R > kTileMaxR; }), Rs.end());
+  } else if (cfg->lj_kernel) Ks.push_back(cfg->lj_kernel);
   else {
     Ks.push_back(MD_LJ_ATOM);
     Ks.push_back(MD_LJ_CELLTILE);
@@ -356,7 +440,7 @@ md_status autotune(md_ctx* c, const md_config* cfg, int* bestR, int* bestK) {
   for (int R : Rs)
     for (int K : Ks) {
       if (Rs.size() * Ks.size() == 1) break;
-      if (K >= MD_LJ_CELLTILE && R > kTileMaxR) continue;
+      if (K >= MD_LJ_CELLTILE && K != MD_LJ_NLIST && R > kTileMaxR) continue;
       if ((st = configure(c, cfg, R, K))) break;
       enqueue_rebuild(c, c->stream, false);
       enqueue_forces(c, c->stream, false, false);
@@ -398,6 +482,7 @@ md_status md_workspace_bytes(const md_forcefield* ff, const md_config* cfg, size
     for (int K = 1; K <= 3; ++K) {
       if (cfg->lj_kernel && cfg->lj_kernel != K) continue;
       if (K >= MD_LJ_CELLTILE && R > kTileMaxR) continue;
+      if (cfg->nl_skin > 0.0 && R > kTileMaxR) continue;
       best = std::max(best, carve(make_plan(ff, cfg, R, K), nullptr, nullptr));
       any = true;
     }
@@ -435,6 +520,8 @@ md_status md_init_system(const md_forcefield* ff, const md_config* cfg, double* 
   c->tau = cfg->tau_fs;
   c->prec = cfg->precision;
   c->use_graph = cfg->use_graph ? 1 : 0;
+  c->nl_skin = cfg->nl_skin;
+  c->nl_every = cfg->nl_skin > 0.0 ? cfg->nl_every : 1;
   c->pos = pos;
   c->vel = vel;
   c->type = type;
@@ -448,7 +535,7 @@ md_status md_init_system(const md_forcefield* ff, const md_config* cfg, double* 
   local.T0 = c->T0.data();
   int R = cfg->cell_div ? cfg->cell_div : 1;
   int K = cfg->lj_kernel ? cfg->lj_kernel : MD_LJ_ATOM;
-  if (!cfg->cell_div || !cfg->lj_kernel) st = autotune(c, &local, &R, &K);
+  if (!cfg->cell_div || (!cfg->lj_kernel && cfg->nl_skin <= 0.0)) st = autotune(c, &local, &R, &K);
   if (!st) st = configure(c, &local, R, K);
   if (!st) {
     enqueue_rebuild(c, c->stream, false);
@@ -473,13 +560,14 @@ md_status md_rebuild_bins(md_ctx* c) {
   if (!c) return MD_ERR_ARG;
   if (c->failed) return MD_ERR_STATE;
   enqueue_rebuild(c, c->stream, false);
+  c->since_build = 0;
   return check_launch(c, "rebuild bins");
 }
 
 md_status md_compute_forces(md_ctx* c, int32_t with_energy) {
   if (!c) return MD_ERR_ARG;
   if (c->failed) return MD_ERR_STATE;
-  enqueue_forces(c, c->stream, false, with_energy != 0);
+  enqueue_forces(c, c->stream, false, with_energy != 0, c->since_build == 0);
   if (with_energy) launch_reduce(c->v, true, false, c->dt, c->tau, c->stream);
   return check_launch(c, "compute forces");
 }
@@ -491,11 +579,14 @@ md_status md_step(md_ctx* c, int32_t n_steps) {
   md_status st;
   for (int32_t k = 0; k < n_steps; ++k) {
     const bool last = k == n_steps - 1;
+    const bool build = next_step_builds(c);
     if (c->use_graph) {
-      if ((st = hip_check(c, hipGraphLaunch(c->exec[last ? 1 : 0], c->stream), "graph launch"))) return st;
+      const int g = (nl_mode(c) && build ? 2 : 0) + (last ? 1 : 0);
+      if ((st = hip_check(c, hipGraphLaunch(c->exec[g], c->stream), "graph launch"))) return st;
     } else {
-      enqueue_step(c, c->stream, last);
+      enqueue_step(c, c->stream, last, build);
     }
+    advance_build_counter(c, build);
   }
   launch_finalize(c->v, c->stream);
   c->step += n_steps;
@@ -519,21 +610,31 @@ md_status md_step_timed(md_ctx* c, int32_t n_steps, double* ms_out) {
   hipStream_t s = c->stream;
   for (int32_t k = 0; k < n_steps; ++k) {
     const bool last = k == n_steps - 1;
+    const bool build = next_step_builds(c);
     hipEvent_t* e = &ev[(size_t)k * P * 2];
     (void)hipEventRecord(e[0], s);
-    launch_bin_count(c->v, true, c->dt, c->ffd, fp32, s);
+    if (build)
+      launch_bin_count(c->v, true, c->dt, c->ffd, fp32, s);
+    else
+      launch_nl_integrate(c->v, c->dt, c->ffd, fp32, s);
     (void)hipEventRecord(e[1], s);
     (void)hipEventRecord(e[2], s);
-    launch_scan(c->v, s);
+    if (build) launch_scan(c->v, s);
     (void)hipEventRecord(e[3], s);
     (void)hipEventRecord(e[4], s);
-    launch_scatter(c->v, s);
+    if (build) launch_scatter(c->v, s);
     (void)hipEventRecord(e[5], s);
     (void)hipEventRecord(e[6], s);
-    launch_rank_payload(c->v, fp32, s);
+    if (build) launch_rank_payload(c->v, fp32, s);
     (void)hipEventRecord(e[7], s);
+    (void)hipEventRecord(e[14], s);
+    if (build && nl_mode(c)) launch_nl_build(c->v, c->ffd, fp32, s);
+    (void)hipEventRecord(e[15], s);
     (void)hipEventRecord(e[8], s);
-    launch_lj(c->v, c->ffd, fp32, c->lj_kernel, last, s);
+    if (nl_mode(c))
+      launch_lj_nl(c->v, c->ffd, fp32, last, build, s);
+    else
+      launch_lj(c->v, c->ffd, fp32, c->lj_kernel, last, s);
     (void)hipEventRecord(e[9], s);
     (void)hipEventRecord(e[10], s);
     launch_bonded(c->v, c->ffd, fp32, true, last, c->dt, s);
@@ -541,6 +642,7 @@ md_status md_step_timed(md_ctx* c, int32_t n_steps, double* ms_out) {
     (void)hipEventRecord(e[12], s);
     launch_reduce(c->v, last, true, c->dt, c->tau, s);
     (void)hipEventRecord(e[13], s);
+    advance_build_counter(c, build);
   }
   launch_finalize(c->v, s);
   c->step += n_steps;
@@ -581,6 +683,11 @@ md_status md_energies(md_ctx* c, md_energy* out) {
   if (err & kErrNonFinite) {
     c->failed = true;
     return fail(c, MD_ERR_NONFINITE, "a position became non-finite");
+  }
+  if (err & (kErrNlMoved | kErrNlFull)) {
+    c->failed = true;
+    return fail(c, MD_ERR_NLIST, (err & kErrNlMoved) ? "an atom moved more than half the skin since the list build"
+                                                     : "an atom had more list neighbours than the list holds");
   }
   return MD_OK;
 }
@@ -641,6 +748,7 @@ const char* md_status_string(md_status s) {
     case MD_ERR_WORKSPACE: return "workspace too small or misaligned";
     case MD_ERR_HIP: return "HIP runtime error";
     case MD_ERR_STATE: return "context in error state";
+    case MD_ERR_NLIST: return "neighbour list invalid (skin exceeded or list full)";
   }
   return "unknown status";
 }

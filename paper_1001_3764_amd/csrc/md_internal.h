@@ -44,9 +44,10 @@ struct BoxDev {
   int32_t cell_off, n_cells;
   int32_t blk_off;        // first per-atom block (kAtomBlock) of this box
   int32_t lj_blk_off;     // first LJ work block of this box
-  int32_t pad;
+  int32_t cell_blk_off;   // first neighbour-list build block (kTileWaves cells) of this box
   double T0;              // <= 0: no thermostat
   double dof;             // 3N - 3
+  int64_t nl_off;         // first entry of this box's neighbour lists
 };
 
 // Force-field constants in the form the kernels use (built on the host).
@@ -102,9 +103,22 @@ struct Views {
   double* lambda;      // [n_boxes] pending Berendsen factor
   double* energy;      // [n_boxes * 8] per-box results
   int32_t* err;        // sticky error word
+  // neighbour-list mode (nl_cap = 0 otherwise)
+  int32_t nl_cap;              // list entries per atom
+  int32_t n_cell_blocks;       // list build blocks (kTileWaves home cells each)
+  const int32_t* cell_blk_box; // [n_cell_blocks] box of each build block
+  uint32_t* nl_list;     // per box, per 64 atoms of sorted order: [nl_cap][64] entries
+                         // (sorted index << 7 | stencil code), entry t of atom s at
+                         // nl_off + (s/64) * 64 * nl_cap + t * 64 + s % 64 (s box-local)
+  int32_t* nl_count;     // [N] list length per sorted slot
+  double* x_build;       // [3N] wrapped positions at the last build (global order)
+  int32_t* slot_of;      // [N] sorted slot of each atom at the last build
+  void* pay_cur;         // [N] payload refreshed every step between builds
+  double nl_rl2;         // (rc + skin)^2
+  double nl_half_skin2;  // (skin / 2)^2
 };
 
-enum ErrBits : int32_t { kErrNonFinite = 1 };
+enum ErrBits : int32_t { kErrNonFinite = 1, kErrNlMoved = 2, kErrNlFull = 4 };
 
 // ---- launchers (md_kernels.hip) ----
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
@@ -119,12 +133,19 @@ void launch_bonded(const Views& v, const FFDev& ff, bool fp32, bool kick, bool e
 void launch_reduce(const Views& v, bool energy, bool thermostat, double dt, double tau,
                    hipStream_t s);
 void launch_finalize(const Views& v, hipStream_t s);
+// neighbour-list mode: update + displacement check + payload refresh between builds
+void launch_nl_integrate(const Views& v, double dt, const FFDev& ff, bool fp32_force, hipStream_t s);
 
 constexpr int kTileHomesMixed = 8;   // home atoms per pass of a mixed cell-tile wave
 
 // ---- launchers (md_lj.hip) ----
 void launch_lj(const Views& v, const FFDev& ff, bool fp32, int kernel, bool energy, hipStream_t s);
 int64_t lj_blocks_for_box(int kernel, int64_t n_atoms, int64_t n_cells);
+// neighbour-list mode: the list build (from the bins) and the LJ force from the list;
+// build_step: the payload of the build is current (else pay_cur is)
+void launch_nl_build(const Views& v, const FFDev& ff, bool fp32, hipStream_t s);
+void launch_lj_nl(const Views& v, const FFDev& ff, bool fp32, bool energy, bool build_step, hipStream_t s);
+constexpr int kLjNlBlock = 256;   // threads per block of the list force kernel (box-aligned)
 constexpr int kTileWaves = 4;     // home cells per block of the cell-tile kernel
 constexpr int kXcds = 8;          // accelerator complex dies of an MI355X (one L2 each)
 constexpr int kTileMaxR = 2;      // stencil radii the cell-tile kernel supports

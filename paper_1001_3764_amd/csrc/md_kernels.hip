@@ -247,6 +247,74 @@ __global__ __launch_bounds__(kAtomBlock) void k_rank_payload(Views v) {
   const double rz = z - ((double)kz + 0.5) * B.edge[2];
   const int32_t tag = (i << 4) | ((int32_t)(v.type[i] & 1) << 3) | (kx & 7);
   store_payload<PayT>(static_cast<PayT*>(v.payload), dst, rx, ry, rz, tag);
+  if (v.nl_cap) {   // neighbour-list mode: where the list build saw the atom
+    v.slot_of[i] = dst;
+    v.x_build[i] = x;
+    v.x_build[N + i] = y;
+    v.x_build[2 * N + i] = z;
+  }
+}
+
+// ---- neighbour-list mode: the update between list builds ----
+__device__ inline double min_image(double d, double L, double invL) { return d - L * rint(d * invL); }
+
+template <typename PayT>
+__device__ inline void refresh_payload(const PayT* build, PayT* cur, int32_t s, double dx, double dy, double dz);
+
+template <>
+__device__ inline void refresh_payload<int4>(const int4* build, int4* cur, int32_t s, double dx, double dy,
+                                             double dz) {
+  const int4 q = build[s];
+  cur[s] = make_int4(q.x + (int)rint(dx * kFix), q.y + (int)rint(dy * kFix), q.z + (int)rint(dz * kFix), q.w);
+}
+template <>
+__device__ inline void refresh_payload<Pay64>(const Pay64* build, Pay64* cur, int32_t s, double dx, double dy,
+                                              double dz) {
+  Pay64 q = build[s];
+  q.x += dx;
+  q.y += dy;
+  q.z += dz;
+  cur[s] = q;
+}
+
+// Berendsen scaling, half kick, drift and wrap as in k_bin_count, without binning; then
+// the displacement since the list build (flagged when above half the skin) moves the
+// atom's build payload to its current place: cur = build + round(d * 2^25) (mixed) or
+// build + d (FP64), so pair differences stay exact integers in the mixed form.
+template <typename F, typename PayT>
+__global__ __launch_bounds__(kAtomBlock) void k_nl_integrate(Views v, const F* __restrict__ f, double dt,
+                                                          FFDev ff) {
+  const int b = v.blk_box[blockIdx.x];
+  const BoxDev& B = v.boxes[b];
+  const int local = ((int)blockIdx.x - B.blk_off) * kAtomBlock + (int)threadIdx.x;
+  if (local >= B.n_atoms) return;
+  const int64_t N = v.N;
+  const int64_t i = (int64_t)B.atom_off + local;
+  const double lam = v.lambda[b];
+  const double h = 0.5 * dt * ff.acc_over_m[v.type[i]];
+  const double vx = lam * v.vel[i] + h * (double)f[i];
+  const double vy = lam * v.vel[N + i] + h * (double)f[N + i];
+  const double vz = lam * v.vel[2 * N + i] + h * (double)f[2 * N + i];
+  v.vel[i] = vx;
+  v.vel[N + i] = vy;
+  v.vel[2 * N + i] = vz;
+  double x = v.pos[i] + dt * vx, y = v.pos[N + i] + dt * vy, z = v.pos[2 * N + i] + dt * vz;
+  if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
+    atomicOr(v.err, (int)kErrNonFinite);
+    x = y = z = 0.0;
+  }
+  x = wrap_coord(x, B.L[0], B.invL[0]);
+  y = wrap_coord(y, B.L[1], B.invL[1]);
+  z = wrap_coord(z, B.L[2], B.invL[2]);
+  v.pos[i] = x;
+  v.pos[N + i] = y;
+  v.pos[2 * N + i] = z;
+  const double dx = min_image(x - v.x_build[i], B.L[0], B.invL[0]);
+  const double dy = min_image(y - v.x_build[N + i], B.L[1], B.invL[1]);
+  const double dz = min_image(z - v.x_build[2 * N + i], B.L[2], B.invL[2]);
+  if (dx * dx + dy * dy + dz * dz > v.nl_half_skin2) atomicOr(v.err, (int)kErrNlMoved);
+  refresh_payload<PayT>(static_cast<const PayT*>(v.payload), static_cast<PayT*>(v.pay_cur), v.slot_of[i], dx, dy,
+                        dz);
 }
 
 // ---- bonded terms ----
@@ -611,6 +679,14 @@ void launch_bonded(const Views& v, const FFDev& ff, bool fp32, bool kick, bool e
 void launch_reduce(const Views& v, bool energy, bool thermostat, double dt, double tau, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce, dim3(v.n_boxes), dim3(256), 0, s, v, energy ? 1 : 0, thermostat ? 1 : 0,
                      dt, tau);
+}
+
+void launch_nl_integrate(const Views& v, double dt, const FFDev& ff, bool fp32_force, hipStream_t s) {
+  dim3 g(v.n_atom_blocks), blk(kAtomBlock);
+  if (fp32_force)
+    hipLaunchKernelGGL((k_nl_integrate<float, int4>), g, blk, 0, s, v, (const float*)v.f_tot, dt, ff);
+  else
+    hipLaunchKernelGGL((k_nl_integrate<double, Pay64>), g, blk, 0, s, v, (const double*)v.f_tot, dt, ff);
 }
 
 void launch_finalize(const Views& v, hipStream_t s) {

@@ -673,6 +673,222 @@ void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
   if (ENERGY) block_energy<kTileWaves>(e, es, w, red, v.part_lj + (int64_t)blk * 3);
 }
 
+// ---------------------------------------------------------------------------------
+// Neighbour-list mode (Sections 3.1-3.2: the paper's list, rebuilt every few steps).
+//
+// Build: one wave per home cell, exactly as the cell tile streams its candidates, but a
+// pair closer than rc + skin (and not excluded) appends the candidate's list entry to the
+// home atom's list instead of computing a force.  Lists are stored per 64 atoms of
+// sorted order, entry-major ([nl_cap][64]), so that the force kernel's 64 lanes read 64
+// consecutive words per step.
+template <bool FP64, int KMAX>
+__global__ __launch_bounds__(64 * kTileWaves) void k_nl_build(Views v, FFDev ff) {
+  using PayT = std::conditional_t<FP64, Pay64, int4>;
+  using Q = std::conditional_t<FP64, double, int>;
+  __shared__ uint32_t list[kTileWaves][kListCap];
+  __shared__ Shift<Q> shifts[kMaxStencil];
+
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const int ln = lane();
+  const int per_xcd = (int)gridDim.x / kXcds;
+  const int blk = ((int)blockIdx.x % kXcds) * per_xcd + (int)blockIdx.x / kXcds;
+  if (blk >= v.n_cell_blocks) return;
+  const BoxDev& B = v.boxes[v.cell_blk_box[blk]];
+  const int lc = (blk - B.cell_blk_off) * kTileWaves + wave;
+  const bool wact = lc < B.n_cells;
+  const PayT* __restrict__ pay = static_cast<const PayT*>(v.payload);
+  {
+    const int R = v.R, W = 2 * R + 1;
+    const int code = (int)threadIdx.x;
+    if (code < W * W * W) {
+      const int ox = code % W - R, oy = (code / W) % W - R, oz = code / (W * W) - R;
+      if constexpr (FP64)
+        shifts[code] = Shift<Q>{ox * B.edge[0], oy * B.edge[1], oz * B.edge[2]};
+      else
+        shifts[code] = Shift<Q>{ox * B.edge_q[0], oy * B.edge_q[1], oz * B.edge_q[2]};
+    }
+  }
+  int total = 0, resident = 0;
+  if (wact) total = __builtin_amdgcn_readfirstlane(fill_list(v, B, lc, 0, list[wave]));
+  __syncthreads();
+  if (!wact) return;
+  const int hs = __builtin_amdgcn_readfirstlane(v.cell_start[B.cell_off + lc]);
+  const int hn = __builtin_amdgcn_readfirstlane(v.cell_start[B.cell_off + lc + 1]) - hs;
+  // list radius in the payload's units, widened a little: the list may hold extra pairs,
+  // never miss one
+  const double rl2 = v.nl_rl2 * (1.0 + 1e-5);
+  const float rl2s = (float)(rl2 * kFix * kFix);
+  const int cap = v.nl_cap;
+  for (int g0 = 0; g0 < hn; g0 += KMAX) {
+    const int kc = min(KMAX, hn - g0);
+    Q hx[KMAX], hy[KMAX], hz[KMAX];
+    int32_t lo[KMAX], cnt[KMAX];
+    uint32_t span[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      cnt[k] = 0;
+      if (k < kc) {
+        const PayT q = pay[hs + g0 + k];
+        hx[k] = uni(q.x);
+        hy[k] = uni(q.y);
+        hz[k] = uni(q.z);
+        const int32_t i = tag_index(uni(pay_tag(q)));
+        const int32_t c0 = i - i % ff.chain_len;
+        lo[k] = max(i - ff.excl, c0);
+        span[k] = (uint32_t)(min(i + ff.excl, c0 + ff.chain_len - 1) - lo[k]);
+      } else {
+        hx[k] = hy[k] = hz[k] = (Q)0;
+        lo[k] = 0;
+        span[k] = 0xffffffffu;
+      }
+    }
+    for (int c0 = 0; c0 < total; c0 += kListCap) {
+      if (c0 != resident) {
+        fill_list(v, B, lc, c0, list[wave]);
+        resident = c0;
+      }
+      const int cn = min(kListCap, total - c0);
+      for (int t0 = 0; t0 < cn; t0 += 64) {
+        const bool act = t0 + ln < cn;
+        uint32_t ent = 0;
+        Q jx = (Q)0, jy = (Q)0, jz = (Q)0;
+        int32_t jt = 0;
+        if (act) {
+          ent = list[wave][t0 + ln];
+          const PayT q = pay[ent >> 7];
+          const Shift<Q> sh = shifts[ent & 127];
+          jt = pay_tag(q);
+          jx = q.x + sh.x;
+          jy = q.y + sh.y;
+          jz = q.z + sh.z;
+        }
+        const int32_t jidx = tag_index(jt);
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+          if (k < kc) {
+            bool hit;
+            if constexpr (FP64) {
+              const double dx = hx[k] - jx, dy = hy[k] - jy, dz = hz[k] - jz;
+              hit = dx * dx + dy * dy + dz * dz < rl2;
+            } else {
+              const float dx = (float)(hx[k] - jx), dy = (float)(hy[k] - jy), dz = (float)(hz[k] - jz);
+              hit = r2_fix(dx, dy, dz) < rl2s;
+            }
+            hit = hit && act && (uint32_t)(jidx - lo[k]) > span[k];
+            const uint64_t m = __ballot(hit);
+            const int at = cnt[k] + lanes_below(m);
+            if (hit && at < cap) {
+              const int ls = hs + g0 + k - B.atom_off;   // box-local sorted slot of the home
+              v.nl_list[B.nl_off + (int64_t)(ls >> 6) * 64 * cap + (int64_t)at * 64 + (ls & 63)] = ent;
+            }
+            cnt[k] += __popcll(m);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k)
+      if (k < kc && ln == 0) {
+        v.nl_count[hs + g0 + k] = min(cnt[k], cap);
+        if (cnt[k] > cap) atomicOr(v.err, (int)kErrNlFull);
+      }
+  }
+}
+
+// LJ force from the lists: one lane per atom of sorted order, walking its list; the
+// candidate comes from the current payload plus the stencil shift recorded at the
+// build.  Mixed form: FP32 on exact int32 differences, with the cutoff band decided in
+// FP64 (inline: about one list entry in 10^6).
+template <bool FP64, bool ENERGY, bool UNI>
+__global__ __launch_bounds__(kLjNlBlock) void k_lj_nl(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd,
+                                                    const void* payv) {
+  using PayT = std::conditional_t<FP64, Pay64, int4>;
+  using P = std::conditional_t<FP64, double, float>;
+  using Q = std::conditional_t<FP64, double, int>;
+  __shared__ Shift<Q> shifts[kMaxStencil];
+  __shared__ dd red[kLjNlBlock / 64][3];
+  const BoxDev& B = v.boxes[v.lj_blk_box[blockIdx.x]];
+  const int local = ((int)blockIdx.x - B.lj_blk_off) * kLjNlBlock + (int)threadIdx.x;
+  {
+    const int R = v.R, W = 2 * R + 1;
+    const int code = (int)threadIdx.x;
+    if (code < W * W * W) {
+      const int ox = code % W - R, oy = (code / W) % W - R, oz = code / (W * W) - R;
+      if constexpr (FP64)
+        shifts[code] = Shift<Q>{ox * B.edge[0], oy * B.edge[1], oz * B.edge[2]};
+      else
+        shifts[code] = Shift<Q>{ox * B.edge_q[0], oy * B.edge_q[1], oz * B.edge_q[2]};
+    }
+  }
+  __syncthreads();
+  double e = 0.0, es = 0.0, w = 0.0;
+  if (local < B.n_atoms) {
+    const PayT* __restrict__ pay = static_cast<const PayT*>(payv);
+    const int32_t s = B.atom_off + local;
+    const PayT hq = pay[s];
+    const int32_t i = tag_index(pay_tag(hq));
+    const int ti = tag_type(pay_tag(hq));
+    const int n = v.nl_count[s];
+    const uint32_t* __restrict__ row =
+        v.nl_list + B.nl_off + (int64_t)(local >> 6) * 64 * v.nl_cap + (local & 63);
+    const Band bd = make_band(ff.rc2);
+    const float f12_fold = cf.f12[0] / cf.f6[0];
+    // four interleaved partial sums: shorter FP32 summation chains, and four list entries
+    // in flight per lane
+    P ax[4] = {0, 0, 0, 0}, ay[4] = {0, 0, 0, 0}, az[4] = {0, 0, 0, 0};
+    int32_t bmax = 0;
+    for (int t0 = 0; t0 < n; t0 += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int t = t0 + u;
+        if (t < n) {
+          const uint32_t ent = row[(int64_t)t * 64];
+          const PayT q = pay[ent >> 7];
+          const Shift<Q> sh = shifts[ent & 127];
+          const int32_t tj = pay_tag(q);
+          const int tt = UNI ? 0 : ti * 2 + tag_type(tj);
+          if constexpr (FP64) {
+            pair_f64<ENERGY>(hq.x - (q.x + sh.x), hq.y - (q.y + sh.y), hq.z - (q.z + sh.z), true, ff.rc2,
+                             pick(cd.f12, tt), pick(cd.f6, tt), pick(cd.e12, tt), pick(cd.e6, tt),
+                             pick(cd.ecut, tt), ax[u], ay[u], az[u], e, es, w);
+          } else {
+            const int dqx = hq.x - (q.x + sh.x), dqy = hq.y - (q.y + sh.y), dqz = hq.z - (q.z + sh.z);
+            const float r2s = pair_fix<ENERGY, false, UNI>(dqx, dqy, dqz, true, bd,
+                                                           UNI ? f12_fold : pick(cf.f12, tt), pick(cf.f6, tt),
+                                                           pick(cf.e12, tt), pick(cf.e6, tt), pick(cf.ecut, tt),
+                                                           ax[u], ay[u], az[u], e, es, w, bmax);
+            double d[3], r2;
+            if (in_band(r2s, true, bd) && !inside_cutoff_f64(v.pos, v.N, B, i, tag_index(tj), ff.rc2, d, r2)) {
+              // counted above as inside; in the folded form the sums are divided by f6
+              float bx = 0.0f, by = 0.0f, bz = 0.0f;
+              remove_band_pair<ENERGY>(d, r2, pick(cf.f12, tt), pick(cf.f6, tt), pick(cf.e12, tt),
+                                       pick(cf.e6, tt), pick(cf.ecut, tt), bx, by, bz, e, es, w);
+              const float sc = UNI ? 1.0f / cf.f6[0] : 1.0f;
+              ax[u] += bx * sc;
+              ay[u] += by * sc;
+              az[u] += bz * sc;
+            }
+          }
+        }
+      }
+    }
+    P fx = (ax[0] + ax[1]) + (ax[2] + ax[3]);
+    P fy = (ay[0] + ay[1]) + (ay[2] + ay[3]);
+    P fz = (az[0] + az[1]) + (az[2] + az[3]);
+    if constexpr (!FP64) {
+      const float sc = UNI ? kInvFixF * cf.f6[0] : kInvFixF;
+      fx *= sc;
+      fy *= sc;
+      fz *= sc;
+    }
+    P* f = static_cast<P*>(v.f_lj);
+    f[i] = fx;
+    f[v.N + i] = fy;
+    f[2 * v.N + i] = fz;
+  }
+  if (ENERGY) block_energy<kLjNlBlock / 64>(e, es, w, red, v.part_lj + (int64_t)blockIdx.x * 3);
+}
+
 template <typename P>
 LjPair<P> make_pair(const FFDev& ff) {
   LjPair<P> c;
@@ -705,7 +921,32 @@ void launch_tile(const Views& v, const FFDev& ff, const LjPair<float>& cf, const
 
 int64_t lj_blocks_for_box(int kernel, int64_t n_atoms, int64_t n_cells) {
   if (kernel == 2 || kernel == 3) return (n_cells + kTileWaves - 1) / kTileWaves;
+  if (kernel == 4) return (n_atoms + kLjNlBlock - 1) / kLjNlBlock;
   return (n_atoms + kLjAtomBlock - 1) / kLjAtomBlock;
+}
+
+void launch_nl_build(const Views& v, const FFDev& ff, bool fp32, hipStream_t s) {
+  dim3 g((v.n_cell_blocks + kXcds - 1) / kXcds * kXcds), b(64 * kTileWaves);
+  if (fp32)
+    hipLaunchKernelGGL((k_nl_build<false, kTileHomesMixed>), g, b, 0, s, v, ff);
+  else
+    hipLaunchKernelGGL((k_nl_build<true, 4>), g, b, 0, s, v, ff);
+}
+
+void launch_lj_nl(const Views& v, const FFDev& ff, bool fp32, bool energy, bool build_step, hipStream_t s) {
+  const LjPair<float> cf = make_pair<float>(ff);
+  const LjPair<double> cd = make_pair<double>(ff);
+  const void* pay = build_step ? v.payload : v.pay_cur;
+  dim3 g(v.n_lj_blocks), b(kLjNlBlock);
+#define MDK_NL(F64, E, U) hipLaunchKernelGGL((k_lj_nl<F64, E, U>), g, b, 0, s, v, ff, cf, cd, pay)
+  if (fp32) {
+    if (ff.uniform_lj) { if (energy) MDK_NL(false, true, true); else MDK_NL(false, false, true); }
+    else { if (energy) MDK_NL(false, true, false); else MDK_NL(false, false, false); }
+  } else {
+    if (ff.uniform_lj) { if (energy) MDK_NL(true, true, true); else MDK_NL(true, false, true); }
+    else { if (energy) MDK_NL(true, true, false); else MDK_NL(true, false, false); }
+  }
+#undef MDK_NL
 }
 
 void launch_lj(const Views& v, const FFDev& ff, bool fp32, int kernel, bool energy, hipStream_t s) {

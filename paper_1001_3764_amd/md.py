@@ -17,9 +17,9 @@ LIB_PATH = os.environ.get("PAPER_1001_3764_AMD_LIB") or os.path.join(
     os.path.dirname(os.path.abspath(__file__)), "libmd_gfx950.so")
 
 MD_OK, MD_ERR_ARG, MD_ERR_BOX_TOO_SMALL, MD_ERR_NONFINITE = 0, -1, -2, -3
-MD_ERR_WORKSPACE, MD_ERR_HIP, MD_ERR_STATE = -4, -6, -7
+MD_ERR_WORKSPACE, MD_ERR_HIP, MD_ERR_STATE, MD_ERR_NLIST = -4, -6, -7, -8
 MD_PREC_FP64, MD_PREC_MIXED = 0, 1
-MD_LJ_AUTO, MD_LJ_ATOM, MD_LJ_CELLTILE, MD_LJ_CELLTILE_NB = 0, 1, 2, 3
+MD_LJ_AUTO, MD_LJ_ATOM, MD_LJ_CELLTILE, MD_LJ_CELLTILE_NB, MD_LJ_NLIST = 0, 1, 2, 3, 4
 
 _D, _I32, _I64, _P = ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
 
@@ -33,7 +33,8 @@ class md_forcefield(ctypes.Structure):
 class md_config(ctypes.Structure):
     _fields_ = [("n_boxes", _I32), ("chain_len", _I32), ("n_chains", ctypes.POINTER(_I32)),
                 ("box", ctypes.POINTER(_D)), ("T0", ctypes.POINTER(_D)), ("dt_fs", _D), ("tau_fs", _D),
-                ("precision", _I32), ("cell_div", _I32), ("lj_kernel", _I32), ("use_graph", _I32)]
+                ("precision", _I32), ("cell_div", _I32), ("lj_kernel", _I32), ("use_graph", _I32),
+                ("nl_skin", _D), ("nl_every", _I32)]
 
 
 class md_energy(ctypes.Structure):
@@ -118,7 +119,8 @@ def make_forcefield(ff: dict) -> md_forcefield:
 class _Config:
     """md_config plus the host arrays it points to (kept alive together)."""
 
-    def __init__(self, n_chains, boxes, T0, chain_len, dt, tau, precision, cell_div, lj_kernel, use_graph):
+    def __init__(self, n_chains, boxes, T0, chain_len, dt, tau, precision, cell_div, lj_kernel, use_graph,
+                 nl_skin=0.0, nl_every=1):
         self.n_chains = np.ascontiguousarray(n_chains, dtype=np.int32)
         self.box = np.ascontiguousarray(np.asarray(boxes, dtype=np.float64).reshape(-1, 3))
         self.T0 = np.ascontiguousarray(T0, dtype=np.float64)
@@ -134,6 +136,8 @@ class _Config:
         c.cell_div = int(cell_div)
         c.lj_kernel = int(lj_kernel)
         c.use_graph = int(bool(use_graph))
+        c.nl_skin = float(nl_skin)
+        c.nl_every = int(nl_every)
         self.c = c
 
 
@@ -163,8 +167,8 @@ def md_step(ctx, n_steps):
     _check(load().md_step(ctx, int(n_steps)), "md_step", ctx)
 
 
-MD_N_PHASES = 7
-PHASES = ("integrate_bin", "scan", "scatter", "rank_payload", "lj", "bonded_kick", "reduce")
+MD_N_PHASES = 8
+PHASES = ("integrate_bin", "scan", "scatter", "rank_payload", "lj", "bonded_kick", "reduce", "nlist_build")
 
 
 def md_step_timed(ctx, n_steps):
@@ -219,11 +223,14 @@ class MDSystem:
     library owns every computation on them."""
 
     def __init__(self, ff: dict, n_chains, boxes, T0, pos, vel, types, chain_len=300, dt=1.0, tau=100.0,
-                 precision="mixed", cell_div=1, lj_kernel=MD_LJ_ATOM, use_graph=False, device="cuda:0"):
+                 precision="mixed", cell_div=1, lj_kernel=MD_LJ_ATOM, use_graph=False, device="cuda:0",
+                 nl_skin=0.0, nl_every=10):
+        """nl_skin > 0: neighbour-list mode (bins and list rebuilt every nl_every steps)."""
         load()
         self.device = torch.device(device)
         self.ff = make_forcefield(ff)
-        self.cfg = _Config(n_chains, boxes, T0, chain_len, dt, tau, precision, cell_div, lj_kernel, use_graph)
+        self.cfg = _Config(n_chains, boxes, T0, chain_len, dt, tau, precision, cell_div, lj_kernel, use_graph,
+                           nl_skin, nl_every)
         self.n_boxes = self.cfg.c.n_boxes
         pos = np.ascontiguousarray(pos, dtype=np.float64)
         vel = np.ascontiguousarray(vel, dtype=np.float64)
