@@ -833,13 +833,16 @@ __global__ __launch_bounds__(kLjNlBlock) void k_lj_nl(Views v, FFDev ff, LjPair<
         v.nl_list + B.nl_off + (int64_t)(local >> 6) * 64 * v.nl_cap + (local & 63);
     const Band bd = make_band(ff.rc2);
     const float f12_fold = cf.f12[0] / cf.f6[0];
-    // four interleaved partial sums: shorter FP32 summation chains, and four list entries
-    // in flight per lane
-    P ax[4] = {0, 0, 0, 0}, ay[4] = {0, 0, 0, 0}, az[4] = {0, 0, 0, 0};
-    int32_t bmax = 0;
-    for (int t0 = 0; t0 < n; t0 += 4) {
+    // kNlSums interleaved partial sums: shorter FP32 summation chains, and that many list
+    // entries in flight per lane
+    constexpr int kNlSums = FP64 ? 4 : 8;
+    P ax[kNlSums], ay[kNlSums], az[kNlSums];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < kNlSums; ++u) ax[u] = ay[u] = az[u] = (P)0;
+    int32_t bmax = 0;
+    for (int t0 = 0; t0 < n; t0 += kNlSums) {
+#pragma unroll
+      for (int u = 0; u < kNlSums; ++u) {
         const int t = t0 + u;
         if (t < n) {
           const uint32_t ent = row[(int64_t)t * 64];
@@ -872,9 +875,14 @@ __global__ __launch_bounds__(kLjNlBlock) void k_lj_nl(Views v, FFDev ff, LjPair<
         }
       }
     }
-    P fx = (ax[0] + ax[1]) + (ax[2] + ax[3]);
-    P fy = (ay[0] + ay[1]) + (ay[2] + ay[3]);
-    P fz = (az[0] + az[1]) + (az[2] + az[3]);
+    for (int h = kNlSums / 2; h > 0; h >>= 1)   // pairwise
+#pragma unroll
+      for (int u = 0; u < h; ++u) {
+        ax[u] += ax[u + h];
+        ay[u] += ay[u + h];
+        az[u] += az[u + h];
+      }
+    P fx = ax[0], fy = ay[0], fz = az[0];
     if constexpr (!FP64) {
       const float sc = UNI ? kInvFixF * cf.f6[0] : kInvFixF;
       fx *= sc;
