@@ -39,7 +39,11 @@ class OraEnergy(ctypes.Structure):
 
 
 class OraInteg(ctypes.Structure):
-    _fields_ = [("dt", D), ("tau", D), ("T0", D)]
+    _fields_ = [("dt", D), ("tau", D), ("T0", D), ("remove_com", I32)]
+
+
+class OraNH(ctypes.Structure):
+    _fields_ = [("xi", D), ("eta", D), ("e_thermostat", D)]
 
 
 def build(force: bool = False) -> str:
@@ -75,6 +79,9 @@ def lib():
             "ora_dihedral_term": (D, [P, P, P, P, P, P, P]),
             "ora_run": (ctypes.c_int, [P, P, I64, I32, P, P, P, P, P, P, P, P, P, P, P, P, I32, I32,
                                        P, P, P]),
+            "ora_run_leapfrog": (ctypes.c_int, [P, P, P, I64, I32, P, P, P, P, P, P, P, P, P, P, P, P, I32,
+                                                I32, P, P, P]),
+            "ora_com_velocity": (ctypes.c_int, [P, I64, P, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -258,7 +265,43 @@ def dihedral_term(ff, xi, xj, xk, xl):
     return e, f.reshape(4, 3), ph.value
 
 
-def run(ff, pos, vel, frc, types, box, chain_len, n_steps, dt=1.0, tau=100.0, T0=0.0, M=None, R=1):
+def com_velocity(ff, vel, types):
+    """Centre-of-mass velocity of the atoms, sum m v / sum m."""
+    v = _soa(vel)
+    t = np.ascontiguousarray(types, dtype=np.uint8)
+    u = np.zeros(3)
+    s = make_ff(ff)
+    _check(lib().ora_com_velocity(ctypes.byref(s), v.shape[1], _p(v[0]), _p(v[1]), _p(v[2]), _p(t), _p(u)),
+           "ora_com_velocity")
+    return u
+
+
+def run_leapfrog(ff, pos, vel, frc, types, box, chain_len, n_steps, dt=1.0, tau=100.0, T0=0.0, M=None, R=1,
+                 remove_com=False, nh=(0.0, 0.0)):
+    """Leap-frog + Nose-Hoover on copies of (pos, vel, frc): vel holds v(t - dt/2) and frc
+    the force at pos.  nh = (xi, eta) on entry.  Returns (pos, vel, frc, energies) with the
+    energies dict carrying xi, eta and e_thermostat after the last step."""
+    p = _soa(pos).copy()
+    v = _soa(vel).copy()
+    f = _soa(frc).copy()
+    t = np.ascontiguousarray(types, dtype=np.uint8)
+    L = _box(box)
+    Mv = np.ascontiguousarray(grid_dims(L, ff["rc"], R) if M is None else M, dtype=np.int32)
+    e = OraEnergy()
+    ke, T = D(), D()
+    s = make_ff(ff)
+    integ = OraInteg(dt=dt, tau=tau, T0=T0, remove_com=1 if remove_com else 0)
+    st = OraNH(xi=nh[0], eta=nh[1], e_thermostat=0.0)
+    _check(lib().ora_run_leapfrog(ctypes.byref(s), ctypes.byref(integ), ctypes.byref(st), p.shape[1], chain_len,
+                                  _p(p[0]), _p(p[1]), _p(p[2]), _p(v[0]), _p(v[1]), _p(v[2]),
+                                  _p(f[0]), _p(f[1]), _p(f[2]), _p(t), _p(L), _p(Mv), int(R), int(n_steps),
+                                  ctypes.byref(e), ctypes.byref(ke), ctypes.byref(T)), "ora_run_leapfrog")
+    return p, v, f, {**e.as_dict(), "e_kin": ke.value, "temperature": T.value, "xi": st.xi, "eta": st.eta,
+                     "e_thermostat": st.e_thermostat}
+
+
+def run(ff, pos, vel, frc, types, box, chain_len, n_steps, dt=1.0, tau=100.0, T0=0.0, M=None, R=1,
+        remove_com=False):
     """Advance copies of (pos, vel, frc) by n_steps; frc must be the force at pos."""
     p = _soa(pos).copy()
     v = _soa(vel).copy()
@@ -269,7 +312,7 @@ def run(ff, pos, vel, frc, types, box, chain_len, n_steps, dt=1.0, tau=100.0, T0
     e = OraEnergy()
     ke, T = D(), D()
     s = make_ff(ff)
-    integ = OraInteg(dt=dt, tau=tau, T0=T0)
+    integ = OraInteg(dt=dt, tau=tau, T0=T0, remove_com=1 if remove_com else 0)
     _check(lib().ora_run(ctypes.byref(s), ctypes.byref(integ), p.shape[1], chain_len,
                          _p(p[0]), _p(p[1]), _p(p[2]), _p(v[0]), _p(v[1]), _p(v[2]),
                          _p(f[0]), _p(f[1]), _p(f[2]), _p(t), _p(L), _p(Mv), int(R), int(n_steps),
@@ -279,4 +322,4 @@ def run(ff, pos, vel, frc, types, box, chain_len, n_steps, dt=1.0, tau=100.0, T0
 
 __all__ = ["build", "lib", "make_ff", "set_threads", "grid_dims", "wrap", "cell_index", "bin_atoms",
            "lj_brute", "lj_cells", "bonded", "forces", "chain_terms", "compensated_sum", "kinetic", "bond_term",
-           "angle_term", "dihedral_term", "run"]
+           "angle_term", "dihedral_term", "run", "run_leapfrog", "com_velocity"]

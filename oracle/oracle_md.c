@@ -9,7 +9,9 @@
  *   Eq. (6)  dihedral               E = kphi (1 + cos(n phi - phi_s))
  *   Section 3.1  cells of edge >= cutoff, an atom searches its own and the
  *                neighbouring cells; 1-2 and 1-3 chain neighbours are excluded
- *   Section 3.4  time integration (velocity Verlet here; same positions as leap-frog)
+ *   Section 3.4  time integration: velocity Verlet with Berendsen scaling, and the
+ *                paper's leap-frog with the Nose-Hoover extended system
+ *   Section 3    removal of the centre-of-mass velocity
  * The dihedral angle follows the IUPAC convention (trans = 180 deg), the reading under
  * which trans and gauche are minima of Eq. (6) with n = 3, phi_s = 0.
  */
@@ -441,6 +443,32 @@ int ora_kinetic(const ora_ff* ff, int64_t n, const double* vx, const double* vy,
   return 0;
 }
 
+int ora_com_velocity(const ora_ff* ff, int64_t n, const double* vx, const double* vy, const double* vz,
+                     const uint8_t* type, double u[3]) {
+  if (!ff || n < 1 || !u) return -1;
+  nsum P[3] = {{0, 0}, {0, 0}, {0, 0}}, Mt = {0, 0};
+  for (int64_t i = 0; i < n; ++i) {
+    double m = ff->mass[type[i]];
+    nadd(&P[0], m * vx[i]);
+    nadd(&P[1], m * vy[i]);
+    nadd(&P[2], m * vz[i]);
+    nadd(&Mt, m);
+  }
+  for (int d = 0; d < 3; ++d) u[d] = nval(&P[d]) / nval(&Mt);
+  return 0;
+}
+
+static void remove_com_velocity(const ora_ff* ff, int64_t n, double* vx, double* vy, double* vz,
+                                const uint8_t* type) {
+  double u[3];
+  ora_com_velocity(ff, n, vx, vy, vz, type, u);
+  for (int64_t i = 0; i < n; ++i) {
+    vx[i] -= u[0];
+    vy[i] -= u[1];
+    vz[i] -= u[2];
+  }
+}
+
 int ora_run(const ora_ff* ff, const ora_integ* in, int64_t n, int32_t chain_len, double* x,
             double* y, double* z, double* vx, double* vy, double* vz, double* fx, double* fy,
             double* fz, const uint8_t* type, const double L[3], const int32_t M[3], int32_t R,
@@ -469,11 +497,60 @@ int ora_run(const ora_ff* ff, const ora_integ* in, int64_t n, int32_t chain_len,
       vy[i] += h * (a * fy[i]);
       vz[i] += h * (a * fz[i]);
     }
+    if (in->remove_com) remove_com_velocity(ff, n, vx, vy, vz, type);
     ora_kinetic(ff, n, vx, vy, vz, type, &ke, &T);
     if (in->T0 > 0 && T > 0) {
       double lam = sqrt(1.0 + in->dt / in->tau * (in->T0 / T - 1.0));
       for (int64_t i = 0; i < n; ++i) { vx[i] *= lam; vy[i] *= lam; vz[i] *= lam; }
     }
+  }
+  if (e_out) *e_out = e;
+  if (ke_out) *ke_out = ke;
+  if (t_out) *t_out = T;
+  return 0;
+}
+
+int ora_run_leapfrog(const ora_ff* ff, const ora_integ* in, ora_nh* nh, int64_t n, int32_t chain_len,
+                     double* x, double* y, double* z, double* vx, double* vy, double* vz, double* fx,
+                     double* fy, double* fz, const uint8_t* type, const double L[3], const int32_t M[3],
+                     int32_t R, int32_t n_steps, ora_energy* e_out, double* ke_out, double* t_out) {
+  if (!ff || !in || n < 2 || n_steps < 0 || !(in->dt > 0) || !(in->tau > 0)) return -1;
+  const double dt = in->dt;
+  const double two_pi = 6.283185307179586;
+  const double omega2 = (two_pi / in->tau) * (two_pi / in->tau);
+  double xi = nh ? nh->xi : 0.0, eta = nh ? nh->eta : 0.0;
+  ora_energy e;
+  memset(&e, 0, sizeof e);
+  double ke = 0, T = 0;
+  for (int32_t step = 0; step < n_steps; ++step) {
+    /* v(t + dt/2) from v(t - dt/2): the friction term -xi v is taken at the middle of
+       the interval, (v(t - dt/2) + v(t + dt/2)) / 2, which gives the division below */
+    const double num = 1.0 - 0.5 * dt * xi, den = 1.0 + 0.5 * dt * xi;
+    for (int64_t i = 0; i < n; ++i) {
+      double a = ACC_UNIT / ff->mass[type[i]];
+      vx[i] = (num * vx[i] + dt * (a * fx[i])) / den;
+      vy[i] = (num * vy[i] + dt * (a * fy[i])) / den;
+      vz[i] = (num * vz[i] + dt * (a * fz[i])) / den;
+      x[i] += dt * vx[i];
+      y[i] += dt * vy[i];
+      z[i] += dt * vz[i];
+    }
+    ora_wrap(n, x, y, z, L);
+    int rc = ora_forces(ff, n, chain_len, x, y, z, type, L, M, R, fx, fy, fz, &e);
+    if (rc) return rc;
+    if (in->remove_com) remove_com_velocity(ff, n, vx, vy, vz, type);
+    ora_kinetic(ff, n, vx, vy, vz, type, &ke, &T);
+    if (in->T0 > 0) {
+      /* dxi/dt = omega^2 (T/T0 - 1) with T at the half step between xi(t) and xi(t + dt) */
+      const double xi_next = xi + dt * omega2 * (T / in->T0 - 1.0);
+      eta += 0.5 * dt * (xi + xi_next);
+      xi = xi_next;
+    }
+  }
+  if (nh) {
+    nh->xi = xi;
+    nh->eta = eta;
+    nh->e_thermostat = in->T0 > 0 ? (double)(3 * n - 3) * R_GAS * in->T0 * (xi * xi / (2.0 * omega2) + eta) : 0.0;
   }
   if (e_out) *e_out = e;
   if (ke_out) *ke_out = ke;

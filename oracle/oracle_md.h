@@ -16,7 +16,11 @@
  *     (Section 3.1, Dreiding II);
  *   - bond, angle and dihedral forces and energies (Eqs. 4-6; Section 3.3);
  *   - one velocity-Verlet step with optional Berendsen scaling (Section 3.4
- *     integrates with leap-frog, whose positions are the same).
+ *     integrates with leap-frog, whose positions are the same);
+ *   - one leap-frog step with the Nose-Hoover thermostat (Section 3 opening and
+ *     Section 3.4: leap-frog, NVT through the Nose-Hoover extended system);
+ *   - removal of each box's centre-of-mass velocity (Section 3 opening and the
+ *     COM-removal timing of Section 4; translation only, see ora_integ).
  *
  * Units: Angstrom, fs, g/mol, kcal/mol, K.  Every array is caller-owned host
  * memory; coordinates are structure-of-arrays.  Functions return 0 on success and
@@ -112,19 +116,48 @@ int ora_kinetic(const ora_ff* ff, int64_t n, const double* vx, const double* vy,
 
 typedef struct {
   double dt;     /* fs */
-  double tau;    /* fs, Berendsen coupling time */
+  double tau;    /* fs: Berendsen coupling time (ora_run), Nose-Hoover period tau_T (ora_run_leapfrog) */
   double T0;     /* K; <= 0 disables the thermostat (NVE) */
+  int32_t remove_com;  /* 1: after every step subtract the centre-of-mass velocity,
+                          u = sum m v / sum m, from every velocity (translation only; a
+                          rotation of a periodic box is not a conserved motion) */
 } ora_integ;
+
+/* Centre-of-mass velocity u = sum_i m_i v_i / sum_i m_i (compensated sums, index order). */
+int ora_com_velocity(const ora_ff* ff, int64_t n, const double* vx, const double* vy, const double* vz,
+                     const uint8_t* type, double u[3]);
+
+/* Nose-Hoover state: friction xi (1/fs), its time integral eta, and (output) the energy
+   of the extended variables, dof R T0 (xi^2 / (2 omega^2) + eta), omega = 2 pi / tau. */
+typedef struct {
+  double xi, eta, e_thermostat;
+} ora_nh;
 
 /* n_steps of velocity Verlet on one box.  On entry f holds the total force at x;
    on exit x, v and f are advanced.  Per step: v += dt/2 a; x += dt v; wrap;
-   f = F(x); v += dt/2 a; KE, T; if T0 > 0, v *= lambda with
+   f = F(x); v += dt/2 a; [remove_com: v -= u]; KE, T; if T0 > 0, v *= lambda with
    lambda = sqrt(1 + dt/tau (T0/T - 1)).  e_out / ke_out / t_out (may be null) get
    the energies of the last step (kinetic energy and temperature before scaling). */
 int ora_run(const ora_ff* ff, const ora_integ* in, int64_t n, int32_t chain_len, double* x,
             double* y, double* z, double* vx, double* vy, double* vz, double* fx, double* fy,
             double* fz, const uint8_t* type, const double L[3], const int32_t M[3], int32_t R,
             int32_t n_steps, ora_energy* e_out, double* ke_out, double* t_out);
+
+/* n_steps of leap-frog with the Nose-Hoover thermostat on one box.  Equations of motion:
+   dx/dt = v, dv/dt = F/m - xi v, dxi/dt = omega^2 (T/T0 - 1), deta/dt = xi, with
+   omega = 2 pi / tau (thermostat mass Q = tau^2 T0 / (4 pi^2) per unit dof R).
+   v holds half-step velocities: on entry v(t - dt/2) with f = F(x(t)).  Per step:
+     v <- ((1 - dt/2 xi) v + dt a) / (1 + dt/2 xi)      (friction at mid-interval)
+     x <- wrap(x + dt v);  f = F(x)
+     [remove_com: v <- v - u]
+     KE, T of v (the half-step velocities);
+     if T0 > 0: xi' = xi + dt omega^2 (T/T0 - 1); eta <- eta + dt (xi + xi')/2; xi <- xi'.
+   nh (may be null: start from rest, state discarded) carries xi and eta across calls.
+   Outputs as ora_run. */
+int ora_run_leapfrog(const ora_ff* ff, const ora_integ* in, ora_nh* nh, int64_t n, int32_t chain_len,
+                     double* x, double* y, double* z, double* vx, double* vy, double* vz, double* fx,
+                     double* fy, double* fz, const uint8_t* type, const double L[3], const int32_t M[3],
+                     int32_t R, int32_t n_steps, ora_energy* e_out, double* ke_out, double* t_out);
 
 #ifdef __cplusplus
 }
