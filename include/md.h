@@ -11,8 +11,10 @@
  *   - bonded forces (Section 3.3, Eqs. 3-6): bond, angle and dihedral terms of the
  *     linear chains;
  *   - update (Section 3.4): velocity Verlet (the same positions as the paper's
- *     leap-frog) with optional Berendsen velocity scaling, and per-box kinetic
- *     energy, potential energies and virial summed in compensated double precision.
+ *     leap-frog) with optional Berendsen velocity scaling, or the paper's leap-frog with
+ *     the Nose-Hoover thermostat; optional removal of each box's centre-of-mass velocity
+ *     (Section 3); per-box kinetic energy, potential energies and virial summed in
+ *     compensated double precision.
  *
  * Units: Angstrom, fs, g/mol, kcal/mol, K.
  *
@@ -75,6 +77,19 @@ typedef enum {
                             per atom walking its Verlet list; not a valid lj_kernel request */
 } md_lj_kernel;
 
+typedef enum {
+  MD_INT_VERLET_BERENDSEN = 0, /* velocity Verlet; with T0 > 0, Berendsen scaling
+                                  v <- lambda v, lambda = sqrt(1 + dt/tau (T0/T - 1)), T from the
+                                  full-step velocities */
+  MD_INT_LEAPFROG_NH = 1       /* leap-frog with the Nose-Hoover thermostat (Section 3.4):
+                                  dv/dt = F/m - xi v, dxi/dt = omega^2 (T/T0 - 1), omega = 2 pi / tau.
+                                  Velocities are half-step velocities: the ones passed to init are
+                                  v(-dt/2), and after n steps vel holds v((n - 1/2) dt).  Per step:
+                                  v <- ((1 - dt xi/2) v + dt a) / (1 + dt xi/2); x <- x + dt v;
+                                  forces; [COM removal]; T from v; xi advanced with that T.
+                                  xi starts at 0; with T0 <= 0 it stays 0 (NVE leap-frog) */
+} md_integrator;
+
 /* Force field (Table I, Eqs. 2-6).  Types: 0 = CH2 (C_32), 1 = CH3 (C_33).  LJ pair
    parameters follow Lorentz-Berthelot mixing. */
 typedef struct {
@@ -97,7 +112,9 @@ typedef struct {
   const double* box;          /* host [n_boxes * 3], box edges in A */
   const double* T0;           /* host [n_boxes], thermostat target in K; <= 0: NVE */
   double dt_fs;               /* time step, fs (> 0) */
-  double tau_fs;              /* Berendsen coupling time, fs (> 0) */
+  double tau_fs;              /* thermostat time, fs (> 0): Berendsen coupling time, or the
+                                 Nose-Hoover period tau_T (thermostat mass tau_T^2 T0 / (4 pi^2)
+                                 per degree of freedom and unit gas constant) */
   int32_t precision;          /* md_precision */
   int32_t cell_div;           /* R: cells of edge >= rc / R, (2R+1)^3 cells visited;
                                  1 = the paper's grid (edge >= cutoff), 2 = half cells;
@@ -111,6 +128,12 @@ typedef struct {
                                  that no atom moved more than nl_skin / 2 since the build
                                  (MD_ERR_NLIST otherwise).  0: forces from the cells every step */
   int32_t nl_every;           /* steps between list builds, >= 1 (neighbour-list mode only) */
+  int32_t integrator;         /* md_integrator */
+  int32_t remove_com;         /* 1: after every step subtract each box's centre-of-mass velocity
+                                 sum(m v) / sum(m) (after the drift, before the thermostat reads
+                                 T; translation only: a periodic box has no conserved rotation);
+                                 the reported kinetic energy is then that of the motion relative
+                                 to the centre of mass.  0: no removal */
 } md_config;
 
 /* Per-box results of the most recent energy evaluation. */
@@ -118,10 +141,15 @@ typedef struct {
   double e_lj;           /* truncated LJ energy, kcal/mol */
   double e_lj_shifted;   /* sum over counted pairs of E(r) - E(rc) (reporting only) */
   double e_bond, e_angle, e_dih;
-  double e_kin;          /* kinetic energy before thermostat scaling, kcal/mol */
+  double e_kin;          /* kinetic energy, kcal/mol: velocity Verlet, of the full-step velocities
+                            before Berendsen scaling; leap-frog, of the half-step velocities */
   double temperature;    /* K, 3N - 3 degrees of freedom */
   double virial;         /* sum over interactions of r . F (LJ + bonded), kcal/mol */
   int64_t step;          /* steps taken since init */
+  double nh_xi;          /* Nose-Hoover friction xi for the next step, 1/fs (0 otherwise) */
+  double e_thermostat;   /* Nose-Hoover extended-system energy dof R T0 (xi^2 / (2 omega^2) + eta),
+                            eta = time integral of xi, kcal/mol; KE + PE + e_thermostat is
+                            conserved (0 for velocity Verlet) */
 } md_energy;
 
 typedef struct md_ctx md_ctx;
@@ -154,7 +182,7 @@ md_status md_rebuild_bins(md_ctx* ctx);
    (read them with md_energies). */
 md_status md_compute_forces(md_ctx* ctx, int32_t with_energy);
 
-/* Advance every box by n_steps (>= 0) velocity-Verlet steps with the bins rebuilt
+/* Advance every box by n_steps (>= 0) steps of the configured integrator with the bins rebuilt
    every step (in neighbour-list mode: every nl_every steps, counted from the last
    build, together with the list); energies are evaluated on the last step.  Enqueues
    only. */
@@ -162,13 +190,15 @@ md_status md_step(md_ctx* ctx, int32_t n_steps);
 
 /* Phases timed by md_step_timed. */
 enum {
-  MD_PHASE_INTEGRATE_BIN = 0,  /* lambda scaling, half kick, drift, wrap, cell index, count */
+  MD_PHASE_INTEGRATE_BIN = 0,  /* velocity update (pending Berendsen factor and COM velocity,
+                                  half kick, or the leap-frog kick), drift, wrap, cell index, count */
   MD_PHASE_SCAN = 1,           /* exclusive scan of the cell counts */
   MD_PHASE_SCATTER = 2,        /* unordered cell lists */
   MD_PHASE_RANK = 3,           /* ordered cell lists and the sorted payload */
   MD_PHASE_LJ = 4,             /* Lennard-Jones forces */
-  MD_PHASE_BONDED = 5,         /* bonded forces, total force, second half kick */
-  MD_PHASE_REDUCE = 6,         /* per-box sums and the thermostat factor */
+  MD_PHASE_BONDED = 5,         /* bonded forces, total force, second half kick (velocity Verlet),
+                                  kinetic energy and momentum partial sums */
+  MD_PHASE_REDUCE = 6,         /* per-box sums, the thermostat and the COM velocity */
   MD_PHASE_NLIST = 7,          /* neighbour-list build (neighbour-list mode, build steps only) */
   MD_N_PHASES = 8
 };

@@ -37,6 +37,9 @@ struct md_ctx {
   // graphs: [energy] for the cell path; [2 * build + energy] in neighbour-list mode
   hipGraph_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
   hipGraphExec_t exec[4] = {nullptr, nullptr, nullptr, nullptr};
+  int integrator = MD_INT_VERLET_BERENDSEN;
+  int remove_com = 0;
+  std::vector<double> box_mass;   // total mass of each box (from the types at init)
   double nl_skin = 0.0;      // > 0: neighbour-list mode
   int nl_every = 1;
   int since_build = 0;       // steps since the last list build
@@ -86,6 +89,11 @@ md_status validate(const md_forcefield* ff, const md_config* cfg, std::string* w
   if (cfg->precision != MD_PREC_FP64 && cfg->precision != MD_PREC_MIXED) { *why = "bad precision"; return MD_ERR_ARG; }
   if (cfg->cell_div < 0 || cfg->cell_div > 3) { *why = "cell_div must be 0..3"; return MD_ERR_ARG; }
   if (cfg->lj_kernel < 0 || cfg->lj_kernel > 3) { *why = "lj_kernel must be 0..3"; return MD_ERR_ARG; }
+  if (cfg->integrator != MD_INT_VERLET_BERENDSEN && cfg->integrator != MD_INT_LEAPFROG_NH) {
+    *why = "integrator must be MD_INT_VERLET_BERENDSEN or MD_INT_LEAPFROG_NH";
+    return MD_ERR_ARG;
+  }
+  if (cfg->remove_com != 0 && cfg->remove_com != 1) { *why = "remove_com must be 0 or 1"; return MD_ERR_ARG; }
   if (!(cfg->nl_skin >= 0.0) || !std::isfinite(cfg->nl_skin)) { *why = "nl_skin must be >= 0"; return MD_ERR_ARG; }
   if (cfg->nl_skin > 0.0 && cfg->nl_every < 1) { *why = "nl_every must be >= 1"; return MD_ERR_ARG; }
   if (cfg->nl_skin > 0.0 && cfg->cell_div > kTileMaxR) { *why = "neighbour lists need cell_div <= 2"; return MD_ERR_ARG; }
@@ -232,9 +240,9 @@ size_t carve(const Plan& p, char* base, Views* v) {
   t.f_tot = take(3 * fsz * (size_t)p.N);
   t.scan_tiles = (int32_t*)take(4 * (size_t)p.n_tiles);
   t.part_lj = (dd*)take(sizeof(dd) * 3 * (size_t)p.n_lj_blocks);
-  t.part_bd = (dd*)take(sizeof(dd) * 5 * (size_t)p.n_atom_blocks);
-  t.lambda = (double*)take(8 * (size_t)p.n_boxes);
-  t.energy = (double*)take(64 * (size_t)p.n_boxes);
+  t.part_bd = (dd*)take(sizeof(dd) * kBdParts * (size_t)p.n_atom_blocks);
+  t.thermo = (double*)take(8 * kThermo * (size_t)p.n_boxes);
+  t.energy = (double*)take(8 * kEnergySlots * (size_t)p.n_boxes);
   t.err = (int32_t*)take(4);
   if (p.nl_cap) {
     t.nl_cap = p.nl_cap;
@@ -253,6 +261,7 @@ size_t carve(const Plan& p, char* base, Views* v) {
 FFDev make_ffdev(const md_forcefield* ff, int chain_len) {
   FFDev d{};
   for (int t = 0; t < 2; ++t) {
+    d.mass[t] = ff->mass[t];
     d.acc_over_m[t] = kAccUnit / ff->mass[t];
     d.half_m_over_acc[t] = 0.5 * ff->mass[t] / kAccUnit;
   }
@@ -290,10 +299,20 @@ FFDev make_ffdev(const md_forcefield* ff, int chain_len) {
 
 md_status check_launch(md_ctx* c, const char* what) { return hip_check(c, hipGetLastError(), what); }
 
+StepOpts opts(const md_ctx* c) {
+  StepOpts o;
+  o.dt = c->dt;
+  o.tau = c->tau;
+  o.integrator = c->integrator;
+  o.remove_com = c->remove_com;
+  return o;
+}
+
 // Lays out the workspace for stencil radius R and kernel k, uploads the tables and
 // clears the counters.  Does not touch positions or velocities.
 md_status configure(md_ctx* c, const md_config* cfg, int R, int kernel) {
   Plan p = make_plan(&c->ff, cfg, R, kernel);
+  for (int b = 0; b < p.n_boxes; ++b) p.boxes[b].inv_mass = 1.0 / c->box_mass[b];
   Views v{};
   const size_t need = carve(p, nullptr, nullptr);
   if (need > c->ws_bytes) return fail(c, MD_ERR_WORKSPACE, "workspace too small for this configuration");
@@ -332,10 +351,14 @@ md_status configure(md_ctx* c, const md_config* cfg, int R, int kernel) {
       (st = hip_check(c, hipMemcpy((void*)v.cell_blk_box, cb.data(), 4 * cb.size(), hipMemcpyHostToDevice),
                       "upload list build block table")))
     return st;
+  std::vector<double> th((size_t)kThermo * p.n_boxes, 0.0);
+  for (int b = 0; b < p.n_boxes; ++b) th[(size_t)b * kThermo + kThPre] = th[(size_t)b * kThermo + kThPost] = 1.0;
+  if ((st = hip_check(c, hipMemcpy(v.thermo, th.data(), 8 * th.size(), hipMemcpyHostToDevice),
+                      "upload integrator state")))
+    return st;
   launch_fill_i32(v.cnt, p.C, 0, c->stream);
   launch_fill_i32(v.err, 1, 0, c->stream);
-  launch_fill_f64(v.lambda, p.n_boxes, 1.0, c->stream);
-  launch_fill_f64(v.energy, 8 * (int64_t)p.n_boxes, 0.0, c->stream);
+  launch_fill_f64(v.energy, kEnergySlots * (int64_t)p.n_boxes, 0.0, c->stream);
   if ((st = check_launch(c, "clear workspace"))) return st;
   c->v = v;
   c->hboxes = p.boxes;
@@ -350,33 +373,39 @@ bool nl_mode(const md_ctx* c) { return c->v.nl_cap > 0; }
 // Bins (and, in neighbour-list mode, the list) from the current positions.
 void enqueue_rebuild(md_ctx* c, hipStream_t s, bool kick) {
   const bool fp32 = c->prec == MD_PREC_MIXED;
-  launch_bin_count(c->v, kick, c->dt, c->ffd, fp32, s);
+  launch_bin_count(c->v, kick, opts(c), c->ffd, fp32, s);
   launch_scan(c->v, s);
   launch_scatter(c->v, s);
   launch_rank_payload(c->v, fp32, s);
   if (nl_mode(c)) launch_nl_build(c->v, c->ffd, fp32, s);
 }
 
+BondedMode bonded_mode(const md_ctx* c, bool step) {
+  if (!step) return kBondedForces;
+  return c->integrator == MD_INT_LEAPFROG_NH ? kBondedLeapfrog : kBondedVerletKick;
+}
+
 // build_step: the payload of the last rebuild is current (neighbour-list mode).
+// kick: part of a step (the bonded kernel then kicks or reads the velocities).
 void enqueue_forces(md_ctx* c, hipStream_t s, bool kick, bool energy, bool build_step = true) {
   const bool fp32 = c->prec == MD_PREC_MIXED;
   if (nl_mode(c))
     launch_lj_nl(c->v, c->ffd, fp32, energy, build_step, s);
   else
     launch_lj(c->v, c->ffd, fp32, c->lj_kernel, energy, s);
-  launch_bonded(c->v, c->ffd, fp32, kick, energy, c->dt, s);
+  launch_bonded(c->v, c->ffd, fp32, bonded_mode(c, kick), energy, kick && c->remove_com, c->dt, s);
 }
 
 // One step.  build: rebuild bins and list (always true for the cell path).
 void enqueue_step(md_ctx* c, hipStream_t s, bool energy, bool build = true) {
   if (nl_mode(c) && !build) {
-    launch_nl_integrate(c->v, c->dt, c->ffd, c->prec == MD_PREC_MIXED, s);
+    launch_nl_integrate(c->v, opts(c), c->ffd, c->prec == MD_PREC_MIXED, s);
     enqueue_forces(c, s, true, energy, false);
   } else {
     enqueue_rebuild(c, s, true);
     enqueue_forces(c, s, true, energy, true);
   }
-  launch_reduce(c->v, energy, true, c->dt, c->tau, s);
+  launch_reduce(c->v, energy, true, opts(c), s);
 }
 
 // Whether the next step rebuilds bins and list (a list serves nl_every force evaluations).
@@ -520,6 +549,8 @@ md_status md_init_system(const md_forcefield* ff, const md_config* cfg, double* 
   c->tau = cfg->tau_fs;
   c->prec = cfg->precision;
   c->use_graph = cfg->use_graph ? 1 : 0;
+  c->integrator = cfg->integrator;
+  c->remove_com = cfg->remove_com;
   c->nl_skin = cfg->nl_skin;
   c->nl_every = cfg->nl_skin > 0.0 ? cfg->nl_every : 1;
   c->pos = pos;
@@ -529,6 +560,27 @@ md_status md_init_system(const md_forcefield* ff, const md_config* cfg, double* 
   c->ws_bytes = ws_bytes;
   c->stream = (hipStream_t)stream;
   c->ffd = make_ffdev(ff, cfg->chain_len);
+  {
+    // total mass per box, for the centre-of-mass velocity
+    c->N = 0;
+    for (int b = 0; b < cfg->n_boxes; ++b) c->N += (int64_t)cfg->n_chains[b] * cfg->chain_len;
+    std::vector<uint8_t> ht((size_t)c->N);
+    st = hip_check(c, hipStreamSynchronize(c->stream), "sync");
+    if (!st) st = hip_check(c, hipMemcpy(ht.data(), type, (size_t)c->N, hipMemcpyDeviceToHost), "read types");
+    if (st) {
+      std::fprintf(stderr, "md_init_system: %s\n", c->last_error.c_str());
+      delete c;
+      return st;
+    }
+    int64_t a = 0;
+    for (int b = 0; b < cfg->n_boxes; ++b) {
+      const int64_t n = (int64_t)cfg->n_chains[b] * cfg->chain_len;
+      double m = 0.0;
+      for (int64_t i = 0; i < n; ++i) m += ff->mass[ht[a + i] & 1];
+      c->box_mass.push_back(m);
+      a += n;
+    }
+  }
   md_config local = *cfg;
   local.n_chains = c->n_chains.data();
   local.box = c->box.data();
@@ -540,7 +592,7 @@ md_status md_init_system(const md_forcefield* ff, const md_config* cfg, double* 
   if (!st) {
     enqueue_rebuild(c, c->stream, false);
     enqueue_forces(c, c->stream, false, true);
-    launch_reduce(c->v, true, false, c->dt, c->tau, c->stream);
+    launch_reduce(c->v, true, false, opts(c), c->stream);
     st = check_launch(c, "initial forces");
   }
   if (!st && c->use_graph) st = capture_graphs(c);
@@ -568,7 +620,7 @@ md_status md_compute_forces(md_ctx* c, int32_t with_energy) {
   if (!c) return MD_ERR_ARG;
   if (c->failed) return MD_ERR_STATE;
   enqueue_forces(c, c->stream, false, with_energy != 0, c->since_build == 0);
-  if (with_energy) launch_reduce(c->v, true, false, c->dt, c->tau, c->stream);
+  if (with_energy) launch_reduce(c->v, true, false, opts(c), c->stream);
   return check_launch(c, "compute forces");
 }
 
@@ -588,7 +640,7 @@ md_status md_step(md_ctx* c, int32_t n_steps) {
     }
     advance_build_counter(c, build);
   }
-  launch_finalize(c->v, c->stream);
+  launch_finalize(c->v, opts(c), c->stream);
   c->step += n_steps;
   return check_launch(c, "step");
 }
@@ -614,9 +666,9 @@ md_status md_step_timed(md_ctx* c, int32_t n_steps, double* ms_out) {
     hipEvent_t* e = &ev[(size_t)k * P * 2];
     (void)hipEventRecord(e[0], s);
     if (build)
-      launch_bin_count(c->v, true, c->dt, c->ffd, fp32, s);
+      launch_bin_count(c->v, true, opts(c), c->ffd, fp32, s);
     else
-      launch_nl_integrate(c->v, c->dt, c->ffd, fp32, s);
+      launch_nl_integrate(c->v, opts(c), c->ffd, fp32, s);
     (void)hipEventRecord(e[1], s);
     (void)hipEventRecord(e[2], s);
     if (build) launch_scan(c->v, s);
@@ -637,14 +689,14 @@ md_status md_step_timed(md_ctx* c, int32_t n_steps, double* ms_out) {
       launch_lj(c->v, c->ffd, fp32, c->lj_kernel, last, s);
     (void)hipEventRecord(e[9], s);
     (void)hipEventRecord(e[10], s);
-    launch_bonded(c->v, c->ffd, fp32, true, last, c->dt, s);
+    launch_bonded(c->v, c->ffd, fp32, bonded_mode(c, true), last, c->remove_com != 0, c->dt, s);
     (void)hipEventRecord(e[11], s);
     (void)hipEventRecord(e[12], s);
-    launch_reduce(c->v, last, true, c->dt, c->tau, s);
+    launch_reduce(c->v, last, true, opts(c), s);
     (void)hipEventRecord(e[13], s);
     advance_build_counter(c, build);
   }
-  launch_finalize(c->v, s);
+  launch_finalize(c->v, opts(c), s);
   c->step += n_steps;
   st = check_launch(c, "timed step");
   if (!st) st = hip_check(c, hipStreamSynchronize(s), "timed step sync");
@@ -663,13 +715,13 @@ md_status md_energies(md_ctx* c, md_energy* out) {
   if (!c || !out) return MD_ERR_ARG;
   md_status st;
   if ((st = hip_check(c, hipStreamSynchronize(c->stream), "sync"))) return st;
-  std::vector<double> e(8 * (size_t)c->n_boxes);
+  std::vector<double> e((size_t)kEnergySlots * c->n_boxes);
   int32_t err = 0;
   if ((st = hip_check(c, hipMemcpy(e.data(), c->v.energy, 8 * e.size(), hipMemcpyDeviceToHost), "read energies")))
     return st;
   if ((st = hip_check(c, hipMemcpy(&err, c->v.err, 4, hipMemcpyDeviceToHost), "read error word"))) return st;
   for (int b = 0; b < c->n_boxes; ++b) {
-    const double* q = &e[8 * (size_t)b];
+    const double* q = &e[(size_t)kEnergySlots * b];
     out[b].e_lj = q[0];
     out[b].e_lj_shifted = q[1];
     out[b].e_bond = q[2];
@@ -679,6 +731,8 @@ md_status md_energies(md_ctx* c, md_energy* out) {
     out[b].temperature = q[6];
     out[b].virial = q[7];
     out[b].step = c->step;
+    out[b].nh_xi = q[8];
+    out[b].e_thermostat = q[9];
   }
   if (err & kErrNonFinite) {
     c->failed = true;

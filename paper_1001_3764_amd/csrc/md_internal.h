@@ -47,11 +47,13 @@ struct BoxDev {
   int32_t cell_blk_off;   // first neighbour-list build block (kTileWaves cells) of this box
   double T0;              // <= 0: no thermostat
   double dof;             // 3N - 3
+  double inv_mass;        // 1 / total mass of the box
   int64_t nl_off;         // first entry of this box's neighbour lists
 };
 
 // Force-field constants in the form the kernels use (built on the host).
 struct FFDev {
+  double mass[2];         // g/mol
   double acc_over_m[2];   // kAccUnit / mass
   double half_m_over_acc[2];  // m / (2 kAccUnit): kinetic energy factor
   // LJ per type pair t = ti * 2 + tj:
@@ -99,9 +101,9 @@ struct Views {
   void* f_tot;         // [3N] total force, prec
   int32_t* scan_tiles; // [n_tiles]
   dd* part_lj;         // [n_lj_blocks * 3]: E_lj, E_lj_shifted, W_lj
-  dd* part_bd;         // [n_atom_blocks * 5]: E_b, E_a, E_d, W_b, KE
-  double* lambda;      // [n_boxes] pending Berendsen factor
-  double* energy;      // [n_boxes * 8] per-box results
+  dd* part_bd;         // [n_atom_blocks * kBdParts]: E_b, E_a, E_d, W_b, KE, momentum xyz
+  double* thermo;      // [n_boxes * kThermo] integrator state per box (ThermoSlot)
+  double* energy;      // [n_boxes * kEnergySlots] per-box results
   int32_t* err;        // sticky error word
   // neighbour-list mode (nl_cap = 0 otherwise)
   int32_t nl_cap;              // list entries per atom
@@ -120,21 +122,45 @@ struct Views {
 
 enum ErrBits : int32_t { kErrNonFinite = 1, kErrNlMoved = 2, kErrNlFull = 4 };
 
+constexpr int kBdParts = 8;      // block partials of the bonded kernel
+constexpr int kEnergySlots = 10; // per box: E_lj, E_lj_shifted, E_b, E_a, E_d, KE, T, W, xi, E_thermostat
+
+// Integrator state per box.  The velocity update of the next step is
+//   v <- post * (pre * (v - u) + k dt a)
+// with k = 1/2 (velocity Verlet: pre = the pending Berendsen factor, post = 1) or k = 1
+// (leap-frog: pre = 1 - dt xi / 2, post = 1 / (1 + dt xi / 2)); u is the centre-of-mass
+// velocity still to be removed (0 unless removal is on).
+enum ThermoSlot { kThPre = 0, kThXi = 1, kThEta = 2, kThPost = 3, kThU = 4, kThermo = 8 };
+enum Integrator { kVerletBerendsen = 0, kLeapfrogNoseHoover = 1 };
+
+// What the bonded kernel does with the velocities: nothing (forces only), the second
+// velocity-Verlet half kick, or (leap-frog) read them for the kinetic energy.
+enum BondedMode { kBondedForces = 0, kBondedVerletKick = 1, kBondedLeapfrog = 2 };
+
+// Step options the per-atom kernels need.
+struct StepOpts {
+  double dt;          // fs
+  double tau;         // Berendsen coupling time or Nose-Hoover period, fs
+  int integrator;     // Integrator
+  int remove_com;     // 1: remove each box's centre-of-mass velocity every step
+};
+
 // ---- launchers (md_kernels.hip) ----
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 void launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
-void launch_bin_count(const Views& v, bool kick, double dt, const FFDev& ff, bool fp32_force,
+void launch_bin_count(const Views& v, bool kick, const StepOpts& o, const FFDev& ff, bool fp32_force,
                       hipStream_t s);
 void launch_scan(const Views& v, hipStream_t s);
 void launch_scatter(const Views& v, hipStream_t s);
 void launch_rank_payload(const Views& v, bool fp32, hipStream_t s);
-void launch_bonded(const Views& v, const FFDev& ff, bool fp32, bool kick, bool energy, double dt,
-                   hipStream_t s);
-void launch_reduce(const Views& v, bool energy, bool thermostat, double dt, double tau,
-                   hipStream_t s);
-void launch_finalize(const Views& v, hipStream_t s);
+void launch_bonded(const Views& v, const FFDev& ff, bool fp32, BondedMode mode, bool energy, bool com,
+                   double dt, hipStream_t s);
+// update: advance the integrator state (thermostat, pending COM velocity) from the sums
+void launch_reduce(const Views& v, bool energy, bool update, const StepOpts& o, hipStream_t s);
+// applies what is pending (Berendsen factor, COM velocity) to the velocities
+void launch_finalize(const Views& v, const StepOpts& o, hipStream_t s);
 // neighbour-list mode: update + displacement check + payload refresh between builds
-void launch_nl_integrate(const Views& v, double dt, const FFDev& ff, bool fp32_force, hipStream_t s);
+void launch_nl_integrate(const Views& v, const StepOpts& o, const FFDev& ff, bool fp32_force, hipStream_t s);
 
 constexpr int kTileHomesMixed = 8;   // home atoms per pass of a mixed cell-tile wave
 

@@ -12,8 +12,12 @@
 // Bonded terms (Section 3.3, Eqs. 4-6): each term is computed once by one lane, its
 // per-atom forces go to LDS, and every atom gathers the terms touching it in a fixed
 // order (no doubled/tripled/quadrupled work, no atomics, bitwise reproducible).
-// Update (Section 3.4): velocity Verlet half-kicks and drift in FP64, Berendsen
-// scaling from the per-box kinetic energy, all sums as double-double.
+// Update (Section 3.4): velocity Verlet half-kicks and drift in FP64 with Berendsen
+// scaling, or the paper's leap-frog with the Nose-Hoover extended system; optional
+// removal of each box's centre-of-mass velocity (Section 3); all sums as double-double.
+// Whatever a step's sums decide (the Berendsen factor, the Nose-Hoover friction, the
+// centre-of-mass velocity) is applied by the next step's first kernel, so a step needs
+// no grid-wide synchronisation beyond kernel boundaries.
 #include "md_internal.h"
 
 namespace mdk {
@@ -41,6 +45,16 @@ __device__ inline int cell_coord(double x, double cinv, int M) {
 
 __device__ inline int lane() { return (int)(threadIdx.x & 63); }
 
+// The velocity update of both integrators, v <- post * (pre * (v - u) + h f), with the
+// per-box factors the last reduction left (ThermoSlot) and h = k dt a / F.
+struct Kick {
+  double pre, post, ux, uy, uz;
+};
+__device__ inline Kick load_kick(const Views& v, int b) {
+  const double* t = v.thermo + (int64_t)b * kThermo;
+  return Kick{t[kThPre], t[kThPost], t[kThU], t[kThU + 1], t[kThU + 2]};
+}
+
 // Slot of this lane's atom inside its cell: one atomic per distinct cell in the
 // wavefront; lanes sharing a cell are ranked by lane order (ballot + popcount).
 __device__ inline int aggregated_slot(int32_t* cnt, int c, bool active) {
@@ -60,9 +74,10 @@ __device__ inline int aggregated_slot(int32_t* cnt, int c, bool active) {
   return my;
 }
 
+// kdt: dt / 2 (velocity Verlet half kick) or dt (leap-frog)
 template <typename F, bool KICK>
 __global__ __launch_bounds__(kAtomBlock) void k_bin_count(Views v, const F* __restrict__ f, double dt,
-                                                        FFDev ff) {
+                                                        double kdt, FFDev ff) {
   const int b = v.blk_box[blockIdx.x];
   const BoxDev& B = v.boxes[b];
   const int local = ((int)blockIdx.x - B.blk_off) * kAtomBlock + (int)threadIdx.x;
@@ -74,11 +89,11 @@ __global__ __launch_bounds__(kAtomBlock) void k_bin_count(Views v, const F* __re
     double x = v.pos[i], y = v.pos[N + i], z = v.pos[2 * N + i];
     bool moved = false;
     if (KICK) {
-      const double lam = v.lambda[b];
-      const double h = 0.5 * dt * ff.acc_over_m[v.type[i]];
-      const double vx = lam * v.vel[i] + h * (double)f[i];
-      const double vy = lam * v.vel[N + i] + h * (double)f[N + i];
-      const double vz = lam * v.vel[2 * N + i] + h * (double)f[2 * N + i];
+      const Kick q = load_kick(v, b);
+      const double h = kdt * ff.acc_over_m[v.type[i]];
+      const double vx = q.post * (q.pre * (v.vel[i] - q.ux) + h * (double)f[i]);
+      const double vy = q.post * (q.pre * (v.vel[N + i] - q.uy) + h * (double)f[N + i]);
+      const double vz = q.post * (q.pre * (v.vel[2 * N + i] - q.uz) + h * (double)f[2 * N + i]);
       v.vel[i] = vx;
       v.vel[N + i] = vy;
       v.vel[2 * N + i] = vz;
@@ -277,24 +292,24 @@ __device__ inline void refresh_payload<Pay64>(const Pay64* build, Pay64* cur, in
   cur[s] = q;
 }
 
-// Berendsen scaling, half kick, drift and wrap as in k_bin_count, without binning; then
+// Velocity update, drift and wrap as in k_bin_count, without binning; then
 // the displacement since the list build (flagged when above half the skin) moves the
 // atom's build payload to its current place: cur = build + round(d * 2^25) (mixed) or
 // build + d (FP64), so pair differences stay exact integers in the mixed form.
 template <typename F, typename PayT>
 __global__ __launch_bounds__(kAtomBlock) void k_nl_integrate(Views v, const F* __restrict__ f, double dt,
-                                                          FFDev ff) {
+                                                          double kdt, FFDev ff) {
   const int b = v.blk_box[blockIdx.x];
   const BoxDev& B = v.boxes[b];
   const int local = ((int)blockIdx.x - B.blk_off) * kAtomBlock + (int)threadIdx.x;
   if (local >= B.n_atoms) return;
   const int64_t N = v.N;
   const int64_t i = (int64_t)B.atom_off + local;
-  const double lam = v.lambda[b];
-  const double h = 0.5 * dt * ff.acc_over_m[v.type[i]];
-  const double vx = lam * v.vel[i] + h * (double)f[i];
-  const double vy = lam * v.vel[N + i] + h * (double)f[N + i];
-  const double vz = lam * v.vel[2 * N + i] + h * (double)f[2 * N + i];
+  const Kick q = load_kick(v, b);
+  const double h = kdt * ff.acc_over_m[v.type[i]];
+  const double vx = q.post * (q.pre * (v.vel[i] - q.ux) + h * (double)f[i]);
+  const double vy = q.post * (q.pre * (v.vel[N + i] - q.uy) + h * (double)f[N + i]);
+  const double vz = q.post * (q.pre * (v.vel[2 * N + i] - q.uz) + h * (double)f[2 * N + i]);
   v.vel[i] = vx;
   v.vel[N + i] = vy;
   v.vel[2 * N + i] = vz;
@@ -363,15 +378,21 @@ __device__ inline V3<P> mi_diff(const double* xs, int a, int b, int stride, cons
   return v3<P>((P)d[0], (P)d[1], (P)d[2]);
 }
 
-template <typename P, bool KICK, bool ENERGY>
+// MODE (BondedMode): forces only, or also the second velocity-Verlet half kick, or (leap-frog)
+// the kinetic energy of the velocities as they stand.  COM: also the box momentum partials.
+template <typename P, int MODE, bool ENERGY, bool COM>
 __global__ __launch_bounds__(kAtomBlock) void k_bonded(Views v, FFDev ff, double dt) {
+  constexpr bool KICK = MODE == kBondedVerletKick;
+  constexpr bool SUMS = MODE != kBondedForces || ENERGY;   // block partials written
+  constexpr int NP = COM ? 8 : 5;
+  static_assert(NP <= kBdParts, "partials");
   constexpr int S = kAtomBlock + 2 * kHalo;       // staged atoms: [g0 - 3, g0 + 256 + 3)
   constexpr int T = kAtomBlock + kHalo;           // term starts:  [g0 - 3, g0 + 256)
   __shared__ double xs[3 * S];
   // per term start u: bond force on its first atom; angle forces on i and k;
   // dihedral forces on i, j and l (the missing atom gets minus the sum)
   __shared__ P fb[3 * T], fai[3 * T], fak[3 * T], fdi[3 * T], fdj[3 * T], fdl[3 * T];
-  __shared__ dd red[kAtomBlock / 64][5];
+  __shared__ dd red[kAtomBlock / 64][NP];
 
   const int b = v.blk_box[blockIdx.x];
   const BoxDev& B = v.boxes[b];
@@ -478,7 +499,7 @@ __global__ __launch_bounds__(kAtomBlock) void k_bonded(Views v, FFDev ff, double
 
   const int t = threadIdx.x;
   const int32_t g = g0 + t;
-  double ke = 0.0;
+  double ke = 0.0, mom[3] = {0.0, 0.0, 0.0};
   if (g < box_end) {
     const int u = t + kHalo;   // term start index of the terms that begin at atom g
     P f[3];
@@ -501,7 +522,7 @@ __global__ __launch_bounds__(kAtomBlock) void k_bonded(Views v, FFDev ff, double
       f[k] += flj[k * N + g];
       ftot[k * N + g] = f[k];
     }
-    if (KICK || ENERGY) {
+    if (SUMS) {
       const int ty = v.type[g];
       double vv[3];
       for (int k = 0; k < 3; ++k) vv[k] = v.vel[k * N + g];
@@ -513,24 +534,33 @@ __global__ __launch_bounds__(kAtomBlock) void k_bonded(Views v, FFDev ff, double
         }
       }
       ke = ff.half_m_over_acc[ty] * (vv[0] * vv[0] + vv[1] * vv[1] + vv[2] * vv[2]);
+      if (COM)
+        for (int k = 0; k < 3; ++k) mom[k] = ff.mass[ty] * vv[k];
     }
   }
-  if (KICK || ENERGY) {
-    // block partials: E_b, E_a, E_d, W_b, KE (double-double, fixed reduction order)
-    dd q[5] = {dd_from(e_b), dd_from(e_a), dd_from(e_d), dd_from(w_b), dd_from(ke)};
-    for (int k = 0; k < 5; ++k)
+  if (SUMS) {
+    // block partials: E_b, E_a, E_d, W_b, KE [, momentum xyz] (double-double, fixed order)
+    dd q[NP];
+    q[0] = dd_from(e_b);
+    q[1] = dd_from(e_a);
+    q[2] = dd_from(e_d);
+    q[3] = dd_from(w_b);
+    q[4] = dd_from(ke);
+    if (COM)
+      for (int k = 0; k < 3; ++k) q[5 + k] = dd_from(mom[k]);
+    for (int k = 0; k < NP; ++k)
       for (int off = 32; off > 0; off >>= 1) {
         dd o{__shfl_xor(q[k].hi, off), __shfl_xor(q[k].lo, off)};
         q[k] = dd_add(q[k], o);
       }
     if (lane() == 0)
-      for (int k = 0; k < 5; ++k) red[threadIdx.x >> 6][k] = q[k];
+      for (int k = 0; k < NP; ++k) red[threadIdx.x >> 6][k] = q[k];
     __syncthreads();
     if (threadIdx.x == 0)
-      for (int k = 0; k < 5; ++k) {
+      for (int k = 0; k < NP; ++k) {
         dd s = red[0][k];
         for (int w = 1; w < kAtomBlock / 64; ++w) s = dd_add(s, red[w][k]);
-        v.part_bd[(int64_t)blockIdx.x * 5 + k] = s;
+        v.part_bd[(int64_t)blockIdx.x * kBdParts + k] = s;
       }
   }
 }
@@ -551,27 +581,45 @@ __device__ dd block_sum(const dd* part, int stride, int k, int first, int count,
   return r;
 }
 
-__global__ __launch_bounds__(256) void k_reduce(Views v, int energy, int thermostat, double dt, double tau) {
+// One block per box: the box's energies, kinetic energy and temperature; with update, the
+// integrator state the next step applies:
+//   velocity Verlet: the Berendsen factor lambda = sqrt(1 + dt/tau (T0/T - 1));
+//   leap-frog: xi' = xi + dt omega^2 (T/T0 - 1), omega = 2 pi / tau, eta += dt (xi + xi')/2,
+//              and the kick factors 1 - dt xi'/2 and 1 / (1 + dt xi'/2);
+//   COM removal: u = P / M, and the kinetic energy of the motion relative to it,
+//              KE - |P|^2 / (2 M).
+__global__ __launch_bounds__(256) void k_reduce(Views v, int energy, int update, StepOpts o) {
   __shared__ dd sh[4];
   const int b = blockIdx.x;
   const BoxDev& B = v.boxes[b];
   const int first = B.blk_off;
   const int count = (B.n_atoms + kAtomBlock - 1) / kAtomBlock;
-  const dd ke = block_sum(v.part_bd, 5, 4, first, count, sh);
-  const double KE = ke.hi + ke.lo;
+  const dd ke = block_sum(v.part_bd, kBdParts, 4, first, count, sh);
+  double KE = ke.hi + ke.lo;
+  const bool com = update && o.remove_com;
+  double u[3] = {0.0, 0.0, 0.0};
+  if (com) {
+    double p[3];
+    for (int k = 0; k < 3; ++k) {
+      const dd s = block_sum(v.part_bd, kBdParts, 5 + k, first, count, sh);
+      p[k] = s.hi + s.lo;
+      u[k] = p[k] * B.inv_mass;
+    }
+    KE -= 0.5 * (p[0] * u[0] + p[1] * u[1] + p[2] * u[2]) / kAccUnit;
+  }
   const double T = 2.0 * KE / (B.dof * kRgas);
-  double* out = v.energy + (int64_t)b * 8;
+  double* out = v.energy + (int64_t)b * kEnergySlots;
   if (energy) {
     const int lfirst = B.lj_blk_off;
     const int lcount = (b + 1 < v.n_boxes ? v.boxes[b + 1].lj_blk_off : v.n_lj_blocks) - lfirst;
     dd q[7];
     q[0] = block_sum(v.part_lj, 3, 0, lfirst, lcount, sh);
     q[1] = block_sum(v.part_lj, 3, 1, lfirst, lcount, sh);
-    q[2] = block_sum(v.part_bd, 5, 0, first, count, sh);
-    q[3] = block_sum(v.part_bd, 5, 1, first, count, sh);
-    q[4] = block_sum(v.part_bd, 5, 2, first, count, sh);
+    q[2] = block_sum(v.part_bd, kBdParts, 0, first, count, sh);
+    q[3] = block_sum(v.part_bd, kBdParts, 1, first, count, sh);
+    q[4] = block_sum(v.part_bd, kBdParts, 2, first, count, sh);
     q[5] = block_sum(v.part_lj, 3, 2, lfirst, lcount, sh);
-    q[6] = block_sum(v.part_bd, 5, 3, first, count, sh);
+    q[6] = block_sum(v.part_bd, kBdParts, 3, first, count, sh);
     if (threadIdx.x == 0) {
       out[0] = q[0].hi + q[0].lo;
       out[1] = q[1].hi + q[1].lo;
@@ -585,25 +633,54 @@ __global__ __launch_bounds__(256) void k_reduce(Views v, int energy, int thermos
   if (threadIdx.x == 0) {
     out[5] = KE;
     out[6] = T;
-    if (thermostat) {
-      double lam = 1.0;
-      if (B.T0 > 0.0 && T > 0.0) lam = sqrt(1.0 + dt / tau * (B.T0 / T - 1.0));
-      v.lambda[b] = lam;
+    double* th = v.thermo + (int64_t)b * kThermo;
+    const double two_pi = 6.283185307179586;
+    const double w2 = (two_pi / o.tau) * (two_pi / o.tau);
+    const bool lf = o.integrator == kLeapfrogNoseHoover;
+    if (update) {
+      if (!lf) {
+        double lam = 1.0;
+        if (B.T0 > 0.0 && T > 0.0) lam = sqrt(1.0 + o.dt / o.tau * (B.T0 / T - 1.0));
+        th[kThPre] = lam;
+      } else if (B.T0 > 0.0) {
+        const double xi = th[kThXi];
+        const double xn = xi + o.dt * w2 * (T / B.T0 - 1.0);
+        th[kThEta] += 0.5 * o.dt * (xi + xn);
+        th[kThXi] = xn;
+        th[kThPre] = 1.0 - 0.5 * o.dt * xn;
+        th[kThPost] = 1.0 / (1.0 + 0.5 * o.dt * xn);
+      }
+      if (com)
+        for (int k = 0; k < 3; ++k) th[kThU + k] = u[k];
     }
+    const double xi = th[kThXi];
+    out[8] = xi;
+    out[9] = lf && B.T0 > 0.0 ? B.dof * kRgas * B.T0 * (xi * xi / (2.0 * w2) + th[kThEta]) : 0.0;
   }
 }
 
-__global__ __launch_bounds__(kAtomBlock) void k_finalize(Views v) {
+// Applies the pending Berendsen factor (velocity Verlet) and COM velocity to v.
+__global__ __launch_bounds__(kAtomBlock) void k_finalize(Views v, int lf) {
   const int b = v.blk_box[blockIdx.x];
   const BoxDev& B = v.boxes[b];
   const int local = ((int)blockIdx.x - B.blk_off) * kAtomBlock + (int)threadIdx.x;
   if (local >= B.n_atoms) return;
   const int64_t N = v.N;
   const int64_t i = (int64_t)B.atom_off + local;
-  const double lam = v.lambda[b];
-  v.vel[i] *= lam;
-  v.vel[N + i] *= lam;
-  v.vel[2 * N + i] *= lam;
+  const double* th = v.thermo + (int64_t)b * kThermo;
+  const double s = lf ? 1.0 : th[kThPre];
+  v.vel[i] = s * (v.vel[i] - th[kThU]);
+  v.vel[N + i] = s * (v.vel[N + i] - th[kThU + 1]);
+  v.vel[2 * N + i] = s * (v.vel[2 * N + i] - th[kThU + 2]);
+}
+
+// After k_finalize: nothing pending (the leap-frog kick factors are state, not pending).
+__global__ void k_clear_pending(double* thermo, int n_boxes, int lf) {
+  for (int b = (int)threadIdx.x; b < n_boxes; b += (int)blockDim.x) {
+    double* th = thermo + (int64_t)b * kThermo;
+    if (!lf) th[kThPre] = 1.0;
+    th[kThU] = th[kThU + 1] = th[kThU + 2] = 0.0;
+  }
 }
 
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t val) {
@@ -632,15 +709,18 @@ void launch_fill_f64(double* p, int64_t n, double v, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, v);
 }
 
-void launch_bin_count(const Views& v, bool kick, double dt, const FFDev& ff, bool fp32_force,
+static double kick_dt(const StepOpts& o) { return o.integrator == kLeapfrogNoseHoover ? o.dt : 0.5 * o.dt; }
+
+void launch_bin_count(const Views& v, bool kick, const StepOpts& o, const FFDev& ff, bool fp32_force,
                       hipStream_t s) {
   dim3 g(v.n_atom_blocks), blk(kAtomBlock);
+  const double kdt = kick_dt(o);
   if (!kick)
-    hipLaunchKernelGGL((k_bin_count<float, false>), g, blk, 0, s, v, (const float*)nullptr, dt, ff);
+    hipLaunchKernelGGL((k_bin_count<float, false>), g, blk, 0, s, v, (const float*)nullptr, o.dt, kdt, ff);
   else if (fp32_force)
-    hipLaunchKernelGGL((k_bin_count<float, true>), g, blk, 0, s, v, (const float*)v.f_tot, dt, ff);
+    hipLaunchKernelGGL((k_bin_count<float, true>), g, blk, 0, s, v, (const float*)v.f_tot, o.dt, kdt, ff);
   else
-    hipLaunchKernelGGL((k_bin_count<double, true>), g, blk, 0, s, v, (const double*)v.f_tot, dt, ff);
+    hipLaunchKernelGGL((k_bin_count<double, true>), g, blk, 0, s, v, (const double*)v.f_tot, o.dt, kdt, ff);
 }
 
 void launch_scan(const Views& v, hipStream_t s) {
@@ -662,36 +742,48 @@ void launch_rank_payload(const Views& v, bool fp32, hipStream_t s) {
     hipLaunchKernelGGL(k_rank_payload<Pay64>, dim3(v.n_atom_blocks), dim3(kAtomBlock), 0, s, v);
 }
 
-void launch_bonded(const Views& v, const FFDev& ff, bool fp32, bool kick, bool energy, double dt,
-                   hipStream_t s) {
+template <typename P>
+void launch_bonded_p(const Views& v, const FFDev& ff, BondedMode mode, bool energy, bool com, double dt,
+                     hipStream_t s) {
   dim3 g(v.n_atom_blocks), b(kAtomBlock);
-#define MDK_BONDED(P, K, E) hipLaunchKernelGGL((k_bonded<P, K, E>), g, b, 0, s, v, ff, dt)
-  if (fp32) {
-    if (kick) { if (energy) MDK_BONDED(float, true, true); else MDK_BONDED(float, true, false); }
-    else { if (energy) MDK_BONDED(float, false, true); else MDK_BONDED(float, false, false); }
+#define MDK_BONDED(M, E, C) hipLaunchKernelGGL((k_bonded<P, M, E, C>), g, b, 0, s, v, ff, dt)
+  if (mode == kBondedForces) {
+    if (energy) MDK_BONDED(kBondedForces, true, false); else MDK_BONDED(kBondedForces, false, false);
+  } else if (mode == kBondedVerletKick) {
+    if (com) { if (energy) MDK_BONDED(kBondedVerletKick, true, true); else MDK_BONDED(kBondedVerletKick, false, true); }
+    else { if (energy) MDK_BONDED(kBondedVerletKick, true, false); else MDK_BONDED(kBondedVerletKick, false, false); }
   } else {
-    if (kick) { if (energy) MDK_BONDED(double, true, true); else MDK_BONDED(double, true, false); }
-    else { if (energy) MDK_BONDED(double, false, true); else MDK_BONDED(double, false, false); }
+    if (com) { if (energy) MDK_BONDED(kBondedLeapfrog, true, true); else MDK_BONDED(kBondedLeapfrog, false, true); }
+    else { if (energy) MDK_BONDED(kBondedLeapfrog, true, false); else MDK_BONDED(kBondedLeapfrog, false, false); }
   }
 #undef MDK_BONDED
 }
 
-void launch_reduce(const Views& v, bool energy, bool thermostat, double dt, double tau, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3(v.n_boxes), dim3(256), 0, s, v, energy ? 1 : 0, thermostat ? 1 : 0,
-                     dt, tau);
-}
-
-void launch_nl_integrate(const Views& v, double dt, const FFDev& ff, bool fp32_force, hipStream_t s) {
-  dim3 g(v.n_atom_blocks), blk(kAtomBlock);
-  if (fp32_force)
-    hipLaunchKernelGGL((k_nl_integrate<float, int4>), g, blk, 0, s, v, (const float*)v.f_tot, dt, ff);
+void launch_bonded(const Views& v, const FFDev& ff, bool fp32, BondedMode mode, bool energy, bool com,
+                   double dt, hipStream_t s) {
+  if (fp32)
+    launch_bonded_p<float>(v, ff, mode, energy, com, dt, s);
   else
-    hipLaunchKernelGGL((k_nl_integrate<double, Pay64>), g, blk, 0, s, v, (const double*)v.f_tot, dt, ff);
+    launch_bonded_p<double>(v, ff, mode, energy, com, dt, s);
 }
 
-void launch_finalize(const Views& v, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(v.n_atom_blocks), dim3(kAtomBlock), 0, s, v);
-  launch_fill_f64(v.lambda, v.n_boxes, 1.0, s);
+void launch_reduce(const Views& v, bool energy, bool update, const StepOpts& o, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce, dim3(v.n_boxes), dim3(256), 0, s, v, energy ? 1 : 0, update ? 1 : 0, o);
+}
+
+void launch_nl_integrate(const Views& v, const StepOpts& o, const FFDev& ff, bool fp32_force, hipStream_t s) {
+  dim3 g(v.n_atom_blocks), blk(kAtomBlock);
+  const double kdt = kick_dt(o);
+  if (fp32_force)
+    hipLaunchKernelGGL((k_nl_integrate<float, int4>), g, blk, 0, s, v, (const float*)v.f_tot, o.dt, kdt, ff);
+  else
+    hipLaunchKernelGGL((k_nl_integrate<double, Pay64>), g, blk, 0, s, v, (const double*)v.f_tot, o.dt, kdt, ff);
+}
+
+void launch_finalize(const Views& v, const StepOpts& o, hipStream_t s) {
+  const int lf = o.integrator == kLeapfrogNoseHoover ? 1 : 0;
+  hipLaunchKernelGGL(k_finalize, dim3(v.n_atom_blocks), dim3(kAtomBlock), 0, s, v, lf);
+  hipLaunchKernelGGL(k_clear_pending, dim3(1), dim3(64), 0, s, v.thermo, v.n_boxes, lf);
 }
 
 }  // namespace mdk

@@ -20,6 +20,7 @@ MD_OK, MD_ERR_ARG, MD_ERR_BOX_TOO_SMALL, MD_ERR_NONFINITE = 0, -1, -2, -3
 MD_ERR_WORKSPACE, MD_ERR_HIP, MD_ERR_STATE, MD_ERR_NLIST = -4, -6, -7, -8
 MD_PREC_FP64, MD_PREC_MIXED = 0, 1
 MD_LJ_AUTO, MD_LJ_ATOM, MD_LJ_CELLTILE, MD_LJ_CELLTILE_NB, MD_LJ_NLIST = 0, 1, 2, 3, 4
+MD_INT_VERLET_BERENDSEN, MD_INT_LEAPFROG_NH = 0, 1
 
 _D, _I32, _I64, _P = ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
 
@@ -34,12 +35,13 @@ class md_config(ctypes.Structure):
     _fields_ = [("n_boxes", _I32), ("chain_len", _I32), ("n_chains", ctypes.POINTER(_I32)),
                 ("box", ctypes.POINTER(_D)), ("T0", ctypes.POINTER(_D)), ("dt_fs", _D), ("tau_fs", _D),
                 ("precision", _I32), ("cell_div", _I32), ("lj_kernel", _I32), ("use_graph", _I32),
-                ("nl_skin", _D), ("nl_every", _I32)]
+                ("nl_skin", _D), ("nl_every", _I32), ("integrator", _I32), ("remove_com", _I32)]
 
 
 class md_energy(ctypes.Structure):
     _fields_ = [("e_lj", _D), ("e_lj_shifted", _D), ("e_bond", _D), ("e_angle", _D), ("e_dih", _D),
-                ("e_kin", _D), ("temperature", _D), ("virial", _D), ("step", _I64)]
+                ("e_kin", _D), ("temperature", _D), ("virial", _D), ("step", _I64), ("nh_xi", _D),
+                ("e_thermostat", _D)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -120,7 +122,7 @@ class _Config:
     """md_config plus the host arrays it points to (kept alive together)."""
 
     def __init__(self, n_chains, boxes, T0, chain_len, dt, tau, precision, cell_div, lj_kernel, use_graph,
-                 nl_skin=0.0, nl_every=1):
+                 nl_skin=0.0, nl_every=1, integrator=MD_INT_VERLET_BERENDSEN, remove_com=False):
         self.n_chains = np.ascontiguousarray(n_chains, dtype=np.int32)
         self.box = np.ascontiguousarray(np.asarray(boxes, dtype=np.float64).reshape(-1, 3))
         self.T0 = np.ascontiguousarray(T0, dtype=np.float64)
@@ -138,6 +140,8 @@ class _Config:
         c.use_graph = int(bool(use_graph))
         c.nl_skin = float(nl_skin)
         c.nl_every = int(nl_every)
+        c.integrator = int(integrator)
+        c.remove_com = int(bool(remove_com))
         self.c = c
 
 
@@ -224,13 +228,17 @@ class MDSystem:
 
     def __init__(self, ff: dict, n_chains, boxes, T0, pos, vel, types, chain_len=300, dt=1.0, tau=100.0,
                  precision="mixed", cell_div=1, lj_kernel=MD_LJ_ATOM, use_graph=False, device="cuda:0",
-                 nl_skin=0.0, nl_every=10):
-        """nl_skin > 0: neighbour-list mode (bins and list rebuilt every nl_every steps)."""
+                 nl_skin=0.0, nl_every=10, integrator="verlet", remove_com=False):
+        """nl_skin > 0: neighbour-list mode (bins and list rebuilt every nl_every steps).
+        integrator: "verlet" (velocity Verlet, Berendsen when T0 > 0) or "leapfrog" (leap-frog,
+        Nose-Hoover when T0 > 0, tau the thermostat period; vel holds half-step velocities).
+        remove_com: subtract each box's centre-of-mass velocity after every step."""
         load()
         self.device = torch.device(device)
         self.ff = make_forcefield(ff)
+        integ = {"verlet": MD_INT_VERLET_BERENDSEN, "leapfrog": MD_INT_LEAPFROG_NH}.get(integrator, integrator)
         self.cfg = _Config(n_chains, boxes, T0, chain_len, dt, tau, precision, cell_div, lj_kernel, use_graph,
-                           nl_skin, nl_every)
+                           nl_skin, nl_every, integ, remove_com)
         self.n_boxes = self.cfg.c.n_boxes
         pos = np.ascontiguousarray(pos, dtype=np.float64)
         vel = np.ascontiguousarray(vel, dtype=np.float64)

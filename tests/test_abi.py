@@ -1,0 +1,129 @@
+"""The C ABI without a GPU: the built library loads and exports every function that
+include/md.h declares, the ctypes mirrors of the structs match the header's layout, and the
+host-side validation behind md_workspace_bytes accepts and rejects what the header says."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "md.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:md_status|const char\*)\s+(md_\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def md():
+    from paper_1001_3764_amd import md as m
+    m.load()
+    return m
+
+
+def test_every_declared_function_is_exported(md):
+    names = declared_functions()
+    assert len(names) >= 15
+    lib = ctypes.CDLL(md.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    out = subprocess.run(["nm", "-D", "--defined-only", md.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    assert set(names) <= exported
+
+
+def test_struct_layouts_match_the_header(md, tmp_path):
+    """sizeof and offsetof of every field, from a C program compiled against md.h."""
+    structs = {"md_forcefield": md.md_forcefield, "md_config": md.md_config, "md_energy": md.md_energy}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "md.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append('printf("%s sizeof %%zu\\n", sizeof(%s));' % (name, name))
+        for field, _ in cls._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (name, field, name, field))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        s, f, v = line.split()
+        got[(s, f)] = int(v)
+    for name, cls in structs.items():
+        assert got[(name, "sizeof")] == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert got[(name, field)] == getattr(cls, field).offset, (name, field)
+
+
+def config(md, n_chains=(10,), box=((44.376, 44.376, 44.376),), T0=(300.0,), **kw):
+    args = dict(chain_len=300, dt=1.0, tau=100.0, precision="mixed", cell_div=1, lj_kernel=1, use_graph=False)
+    args.update(kw)
+    return md._Config(list(n_chains), np.asarray(box, float), list(T0), args.pop("chain_len"), args.pop("dt"),
+                      args.pop("tau"), args.pop("precision"), args.pop("cell_div"), args.pop("lj_kernel"),
+                      args.pop("use_graph"), **args)
+
+
+def workspace(md, ff, cfg):
+    n = ctypes.c_size_t()
+    st = md.load().md_workspace_bytes(ctypes.byref(md.make_forcefield(ff)), ctypes.byref(cfg.c), ctypes.byref(n))
+    return st, n.value
+
+
+def test_workspace_bytes_and_validation(md, ff):
+    st, n = workspace(md, ff, config(md))
+    assert st == md.MD_OK and n > 0
+    # the workspace grows with the system and with the FP64 payload
+    _, n2 = workspace(md, ff, config(md, n_chains=(20,), box=((55.9, 55.9, 55.9),)))
+    _, n64 = workspace(md, ff, config(md, precision="fp64"))
+    assert n2 > n and n64 > n
+    # neighbour-list mode needs the list arrays
+    _, nnl = workspace(md, ff, config(md, cell_div=1, lj_kernel=0, nl_skin=1.0, nl_every=10))
+    assert nnl > n
+    # both integrators and the COM removal are valid
+    for integ in (md.MD_INT_VERLET_BERENDSEN, md.MD_INT_LEAPFROG_NH):
+        for com in (False, True):
+            assert workspace(md, ff, config(md, integrator=integ, remove_com=com))[0] == md.MD_OK
+    bad = [
+        dict(integrator=2),
+        dict(dt=0.0),
+        dict(tau=-1.0),
+        dict(chain_len=3, n_chains=(1000,)),
+        dict(cell_div=4),
+        dict(lj_kernel=4),
+        dict(nl_skin=-0.5),
+        dict(nl_skin=1.0, nl_every=0),
+        dict(T0=(float("nan"),)),
+        dict(box=((44.376, 0.0, 44.376),)),
+    ]
+    for kw in bad:
+        assert workspace(md, ff, config(md, **kw))[0] == md.MD_ERR_ARG, kw
+    cfg = config(md)
+    cfg.c.remove_com = 2
+    assert workspace(md, ff, cfg)[0] == md.MD_ERR_ARG
+    # 25 A box: fewer than three cells of edge >= rc per dimension
+    assert workspace(md, ff, config(md, n_chains=(1,), box=((25.0, 25.0, 25.0),)))[0] == md.MD_ERR_BOX_TOO_SMALL
+
+
+def test_status_strings(md):
+    lib = md.load()
+    for st in (md.MD_OK, md.MD_ERR_ARG, md.MD_ERR_BOX_TOO_SMALL, md.MD_ERR_NONFINITE, md.MD_ERR_WORKSPACE,
+               md.MD_ERR_HIP, md.MD_ERR_STATE, md.MD_ERR_NLIST):
+        s = lib.md_status_string(st).decode()
+        assert s and s != "unknown status"
+    assert lib.md_status_string(12345).decode() == "unknown status"
+    assert lib.md_last_error(None).decode() == ""
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """No CPU fallback: a missing library is an error at load time."""
+    code = ("import os; os.environ['PAPER_1001_3764_AMD_LIB'] = %r\n"
+            "from paper_1001_3764_amd import md\n"
+            "try:\n    md.load()\nexcept RuntimeError as e:\n    print('raised', e)\n" % str(tmp_path / "none.so"))
+    out = subprocess.run(["python3", "-c", code], capture_output=True, text=True, cwd=ROOT, timeout=300)
+    assert "raised" in out.stdout, out.stderr
