@@ -6,7 +6,10 @@ mixed precision (FP32 forces, FP64 state), hipGraph-replayed steps.  Beside it: 
 FP64 GPU form on the same input (FP64 everywhere, no graph, its own autotuned grid and LJ
 kernel), the force error of the mixed form against the FP64 oracle (at the grown melt and
 at the end of the timed run), per-phase kernel times, the roofline position of the
-Lennard-Jones kernel, and the FP64 CPU oracle timed on a bounded sample of the workload.
+Lennard-Jones kernel, the FP64 CPU oracle timed on a bounded sample of the workload, and
+two more forms of the step from the end state of the timed run: Verlet neighbour lists
+(skin 1 A, rebuilt every 10 steps) and the paper's leap-frog + Nose-Hoover integrator with
+the centre-of-mass velocity removed every step.
 
 ``--workload`` selects one of the other presets instead (their own JSON line, same keys):
 melt3M_mixed (NVT throughput, then the NVE energy drift over 1,000 steps), ensemble64_mixed
@@ -113,6 +116,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-nlist", action="store_true", help="skip the neighbour-list form")
+    ap.add_argument("--no-leapfrog", action="store_true", help="skip the leap-frog + Nose-Hoover form")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first copy a device buffer of this many MiB (HBM counter calibration)")
     ap.add_argument("--workload", default="melt300k_mixed",
@@ -216,6 +220,33 @@ def main():
         except Exception as exc:
             log("nlist run failed: %r" % (exc,))
 
+    # ---- the paper's integrator: leap-frog + Nose-Hoover (300 K, tau_T 100 fs) with the COM
+    # velocity removed every step, same grid and kernel as the headline, from its end state ----
+    leapfrog = None
+    if not args.no_leapfrog:
+        try:
+            sl = MDSystem(ff, [melt.n_chains], melt.box[None, :], [wl.T0[0]], pos_prof, vel_prof, melt.types,
+                          chain_len=wl.chain_len, dt=wl.dt_fs, tau=100.0, precision="mixed", cell_div=R,
+                          lj_kernel=kern, use_graph=not args.no_graph, device=dev, integrator="leapfrog",
+                          remove_com=True)
+            sl.step(50)
+            torch.cuda.synchronize(dev)
+            a = time.perf_counter()
+            n_lf = min(args.steps, 2000)
+            sl.step(n_lf)
+            torch.cuda.synchronize(dev)
+            b_ = time.perf_counter()
+            ph = {k: v / 100 for k, v in sl.step_timed(100).items()}
+            e_lf = sl.energies()[0]
+            sl.close()
+            leapfrog = {"value": N * n_lf / (b_ - a), "unit": "atom-steps/s", "steps": n_lf,
+                        "ms_per_step": 1e3 * (b_ - a) / n_lf, "thermostat": "nose-hoover", "tau_T_fs": 100.0,
+                        "remove_com": True, "T_K": e_lf["temperature"], "xi_per_fs": e_lf["nh_xi"],
+                        "phases_ms_avg": {k: round(v, 5) for k, v in ph.items()}}
+            log("leapfrog+NH: %.3f ms/step, %.3e atom-steps/s" % (leapfrog["ms_per_step"], leapfrog["value"]))
+        except Exception as exc:
+            log("leapfrog run failed: %r" % (exc,))
+
     cand, pairs = candidate_and_pair_counts(pos_prof, melt.box, start_prof, M, R, ff["rc"], melt.n_chains,
                                             melt.chain_len)
     lj_ms = phase_avg["lj"]
@@ -307,6 +338,7 @@ def main():
         "cpu_baseline": cpu,
         "cpu_baseline_1thread": cpu1,
         "nlist_form": nlist,
+        "leapfrog_nh_form": leapfrog,
     }
     print(json.dumps(out), flush=True)
 

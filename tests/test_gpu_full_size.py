@@ -118,6 +118,32 @@ def test_melt300k_first_100_steps(ff, melt300k):
     assert out["mixed"][0] <= 1e-4 and out["mixed"][2] == pytest.approx(eo["temperature"], rel=1e-5)
 
 
+def test_melt300k_leapfrog_nose_hoover_50_steps(ff, melt300k):
+    """The paper's integrator at full size: leap-frog + Nose-Hoover (300 K, tau_T 100 fs) with
+    the COM velocity removed every step, mixed precision, autotuned, graph-replayed, against
+    the oracle's 50 steps."""
+    wl = WORKLOADS["melt300k_mixed"]
+    m = melt300k
+    s = system(ff, [m], wl, "mixed", cell_div=0, lj_kernel=0, use_graph=True, integrator="leapfrog",
+               remove_com=True)
+    s.step(50)
+    p, v = s.state()
+    e = s.energies()[0]
+    s.close()
+    f0, _ = O.forces(ff, m.pos, m.types, m.box, 300)
+    po, vo, _, eo = O.run_leapfrog(ff, m.pos, m.vel, f0, m.types, m.box, 300, 50, dt=wl.dt_fs, tau=wl.tau_fs,
+                                   T0=wl.T0[0], remove_com=True)
+    d = p - po
+    d -= m.box[:, None] * np.round(d / m.box[:, None])
+    print("leap-frog + NH after 50 steps: max|dx| %.3e A, max|dv| %.3e, xi %.9e (oracle %.9e), T %.6f (oracle %.6f)"
+          % (np.abs(d).max(), np.abs(v - vo).max(), e["nh_xi"], eo["xi"], e["temperature"], eo["temperature"]),
+          flush=True)
+    assert np.abs(d).max() <= 1e-4
+    assert e["temperature"] == pytest.approx(eo["temperature"], rel=1e-5)
+    assert e["nh_xi"] == pytest.approx(eo["xi"], rel=1e-4)
+    assert e["e_thermostat"] == pytest.approx(eo["e_thermostat"], rel=1e-4)
+
+
 def test_melt3M_bins_and_sampled_forces(ff):
     """3,000,000 atoms at 0.85 g/cm^3: bins bit-exact, every bonded force, 2,000 sampled LJ
     forces."""
