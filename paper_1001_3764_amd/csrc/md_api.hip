@@ -117,7 +117,7 @@ double cell_reach(const md_forcefield* ff, const md_config* cfg) {
   return ff->rc + (cfg->nl_skin > 0.0 ? cfg->nl_skin : 0.0);
 }
 
-constexpr int64_t kMaxScanTiles = (int64_t)kScanBlock * 8;   // k_scan_top: 8 tiles per thread
+constexpr int64_t kMaxScanTiles = (int64_t)kScanBlock * 8;   // k_scan: each tile sums the totals before it
 
 bool grid_ok(const md_forcefield* ff, const md_config* cfg, int R) {
   int64_t cells = 0;

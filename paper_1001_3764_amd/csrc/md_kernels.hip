@@ -4,8 +4,11 @@
 // its cell but an unspecified order -- here that slot is followed by a rank pass so
 // the cell lists come out in ascending atom order, the same every run):
 //   k_bin_count     wrap, cell index, slot = atomic count (one atomic per distinct
-//                   cell per wavefront, lanes ranked with ballot/popcount)
-//   k_scan_*        cell_start = exclusive prefix sum of the counts (three passes)
+//                   cell per wavefront, all issued at once, lanes ranked with
+//                   ballot/popcount)
+//   k_scan_tiles    the total count of each tile of cells
+//   k_scan          cell_start = exclusive prefix sum of the counts (each tile's offset is
+//                   the sum of the totals of the tiles before it)
 //   k_scatter       unordered lists: tmp[cell_start[c] + slot] = atom
 //   k_rank_payload  rank inside the cell = number of smaller atom indices in it;
 //                   writes the ordered list and the cell-centre-relative payload
@@ -55,24 +58,33 @@ __device__ inline Kick load_kick(const Views& v, int b) {
   return Kick{t[kThPre], t[kThPost], t[kThU], t[kThU + 1], t[kThU + 2]};
 }
 
-// Slot of this lane's atom inside its cell: one atomic per distinct cell in the
-// wavefront; lanes sharing a cell are ranked by lane order (ballot + popcount).
+// Slot of this lane's atom inside its cell.  Lanes are grouped by cell in a loop with
+// no memory access (one ballot per distinct cell); then the first lane of every group adds
+// the group's size to the cell's count, all groups in one atomic instruction (one round
+// trip per wavefront), and each lane takes base + its rank in the group (lane order).
 __device__ inline int aggregated_slot(int32_t* cnt, int c, bool active) {
   uint64_t pending = __ballot(active);
-  int my = 0;
   const int ln = lane();
+  const uint64_t below = (1ull << ln) - 1ull;
+  int leader = ln, rank = 0, size = 0;
   while (pending) {
-    const int leader = __ffsll((unsigned long long)pending) - 1;
-    const int lc = __shfl(c, leader);
-    const uint64_t grp = __ballot(active && c == lc);
-    int base = 0;
-    if (ln == leader) base = atomicAdd(&cnt[lc], __popcll(grp));
-    base = __shfl(base, leader);
-    if (active && c == lc) my = base + __popcll(grp & ((1ull << ln) - 1ull));
+    const int l = __ffsll((unsigned long long)pending) - 1;
+    const int lc = __builtin_amdgcn_readlane(c, l);
+    const bool mine = active && c == lc;
+    const uint64_t grp = __ballot(mine);
+    if (mine) {
+      leader = l;
+      rank = __popcll(grp & below);
+      size = __popcll(grp);
+    }
     pending &= ~grp;
   }
-  return my;
+  int base = 0;
+  if (active && ln == leader) base = atomicAdd(&cnt[c], size);
+  base = __shfl(base, leader);
+  return base + rank;
 }
+
 
 // kdt: dt / 2 (velocity Verlet half kick) or dt (leap-frog)
 template <typename F, bool KICK>
@@ -165,31 +177,17 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_tiles(const int32_t* __rest
   if (threadIdx.x == 0) tiles[blockIdx.x] = total;
 }
 
-__global__ __launch_bounds__(kScanBlock) void k_scan_top(int32_t* tiles, int n_tiles, int32_t* cell_start,
-                                                        int64_t C) {
+// Tile b's offset is the sum of tiles[0..b) (each block sums them itself: no separate pass
+// over the tile totals), then the tile's own counts are scanned and cleared for the next
+// binning.
+__global__ __launch_bounds__(kScanBlock) void k_scan(int32_t* __restrict__ cnt, int64_t C,
+                                                    const int32_t* __restrict__ tiles,
+                                                    int32_t* __restrict__ cell_start) {
   __shared__ int sh[33];
-  constexpr int kPer = 8;   // up to kScanBlock * 8 tiles
-  int vals[kPer];
-  int s = 0;
-  for (int k = 0; k < kPer; ++k) {
-    const int t = (int)threadIdx.x * kPer + k;
-    vals[k] = t < n_tiles ? tiles[t] : 0;
-    s += vals[k];
-  }
-  int total;
-  int ex = block_exclusive_scan(s, sh, &total);
-  for (int k = 0; k < kPer; ++k) {
-    const int t = (int)threadIdx.x * kPer + k;
-    if (t < n_tiles) tiles[t] = ex;
-    ex += vals[k];
-  }
-  if (threadIdx.x == 0) cell_start[C] = total;
-}
-
-__global__ __launch_bounds__(kScanBlock) void k_scan_apply(int32_t* __restrict__ cnt, int64_t C,
-                                                          const int32_t* __restrict__ tiles,
-                                                          int32_t* __restrict__ cell_start) {
-  __shared__ int sh[33];
+  int pre = 0;
+  for (int t = (int)threadIdx.x; t < (int)blockIdx.x; t += kScanBlock) pre += tiles[t];
+  int offset;
+  block_exclusive_scan(pre, sh, &offset);
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
   int vals[kScanItems];
   int s = 0;
@@ -198,7 +196,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_apply(int32_t* __restrict__
     s += vals[k];
   }
   int total;
-  int ex = block_exclusive_scan(s, sh, &total) + tiles[blockIdx.x];
+  int ex = block_exclusive_scan(s, sh, &total) + offset;
   for (int k = 0; k < kScanItems; ++k) {
     if (base + k < C) {
       cell_start[base + k] = ex;
@@ -206,6 +204,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_apply(int32_t* __restrict__
     }
     ex += vals[k];
   }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) cell_start[C] = offset + total;
 }
 
 __global__ __launch_bounds__(kAtomBlock) void k_scatter(Views v) {
@@ -723,11 +722,11 @@ void launch_bin_count(const Views& v, bool kick, const StepOpts& o, const FFDev&
     hipLaunchKernelGGL((k_bin_count<double, true>), g, blk, 0, s, v, (const double*)v.f_tot, o.dt, kdt, ff);
 }
 
+static int scan_tiles(const Views& v) { return (int)((v.C + kScanTile - 1) / kScanTile); }
+
 void launch_scan(const Views& v, hipStream_t s) {
-  const int n_tiles = (int)((v.C + kScanTile - 1) / kScanTile);
-  hipLaunchKernelGGL(k_scan_tiles, dim3(n_tiles), dim3(kScanBlock), 0, s, v.cnt, v.C, v.scan_tiles);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlock), 0, s, v.scan_tiles, n_tiles, v.cell_start, v.C);
-  hipLaunchKernelGGL(k_scan_apply, dim3(n_tiles), dim3(kScanBlock), 0, s, v.cnt, v.C, v.scan_tiles,
+  hipLaunchKernelGGL(k_scan_tiles, dim3(scan_tiles(v)), dim3(kScanBlock), 0, s, v.cnt, v.C, v.scan_tiles);
+  hipLaunchKernelGGL(k_scan, dim3(scan_tiles(v)), dim3(kScanBlock), 0, s, v.cnt, v.C, v.scan_tiles,
                      v.cell_start);
 }
 
