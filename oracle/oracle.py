@@ -82,6 +82,9 @@ def lib():
             "ora_run_leapfrog": (ctypes.c_int, [P, P, P, I64, I32, P, P, P, P, P, P, P, P, P, P, P, P, I32,
                                                 I32, P, P, P]),
             "ora_com_velocity": (ctypes.c_int, [P, I64, P, P, P, P, P]),
+            "ora_pair_histogram": (ctypes.c_int, [I64, I32, I32, P, P, P, P, P, D, I32, P]),
+            "ora_dihedral_stats": (ctypes.c_int, [I64, I32, P, P, P, P, I32, P, P]),
+            "ora_chain_shape": (ctypes.c_int, [P, I64, I32, P, P, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -300,6 +303,44 @@ def run_leapfrog(ff, pos, vel, frc, types, box, chain_len, n_steps, dt=1.0, tau=
                      "e_thermostat": st.e_thermostat}
 
 
+def pair_histogram(pos, box, chain_len, excl_depth, rmax, n_bins, cells=True):
+    """Unordered non-excluded pairs per distance bin over [0, rmax) (grid search, or brute
+    force with cells=False).  Positions must be wrapped for the grid search."""
+    p = _soa(pos)
+    L = _box(box)
+    out = np.zeros(int(n_bins), dtype=np.uint64)
+    M = None
+    if cells:
+        M = np.ascontiguousarray(np.floor(L / rmax).astype(np.int32))
+    _check(lib().ora_pair_histogram(p.shape[1], int(chain_len), int(excl_depth), _p(p[0]), _p(p[1]), _p(p[2]),
+                                    _p(L), _p(M) if M is not None else None, float(rmax), int(n_bins), _p(out)),
+           "ora_pair_histogram")
+    return out
+
+
+def dihedral_stats(pos, box, chain_len, n_bins):
+    """(histogram of the IUPAC dihedral angle over (-pi, pi], [trans, gauche+, gauche-])."""
+    p = _soa(pos)
+    L = _box(box)
+    hist = np.zeros(max(int(n_bins), 1), dtype=np.uint64)
+    cls = np.zeros(3, dtype=np.uint64)
+    _check(lib().ora_dihedral_stats(p.shape[1], int(chain_len), _p(p[0]), _p(p[1]), _p(p[2]), _p(L), int(n_bins),
+                                    _p(hist), _p(cls)), "ora_dihedral_stats")
+    return hist[:int(n_bins)], cls
+
+
+def chain_shape(ff, pos, types, box, chain_len):
+    """[n_chains, 4]: mass-weighted Rg^2 and the end-to-end vector of each chain."""
+    p = _soa(pos)
+    t = np.ascontiguousarray(types, dtype=np.uint8)
+    L = _box(box)
+    out = np.zeros((p.shape[1] // int(chain_len), 4))
+    s = make_ff(ff)
+    _check(lib().ora_chain_shape(ctypes.byref(s), p.shape[1], int(chain_len), _p(p[0]), _p(p[1]), _p(p[2]), _p(t),
+                                 _p(L), _p(out)), "ora_chain_shape")
+    return out
+
+
 def run(ff, pos, vel, frc, types, box, chain_len, n_steps, dt=1.0, tau=100.0, T0=0.0, M=None, R=1,
         remove_com=False):
     """Advance copies of (pos, vel, frc) by n_steps; frc must be the force at pos."""
@@ -322,4 +363,5 @@ def run(ff, pos, vel, frc, types, box, chain_len, n_steps, dt=1.0, tau=100.0, T0
 
 __all__ = ["build", "lib", "make_ff", "set_threads", "grid_dims", "wrap", "cell_index", "bin_atoms",
            "lj_brute", "lj_cells", "bonded", "forces", "chain_terms", "compensated_sum", "kinetic", "bond_term",
-           "angle_term", "dihedral_term", "run", "run_leapfrog", "com_velocity"]
+           "angle_term", "dihedral_term", "run", "run_leapfrog", "com_velocity", "pair_histogram", "dihedral_stats",
+           "chain_shape"]

@@ -12,6 +12,7 @@
  *   Section 3.4  time integration: velocity Verlet with Berendsen scaling, and the
  *                paper's leap-frog with the Nose-Hoover extended system
  *   Section 3    removal of the centre-of-mass velocity
+ *   Section 5    pair-distance histogram, dihedral statistics, chain shape
  * The dihedral angle follows the IUPAC convention (trans = 180 deg), the reading under
  * which trans and gauche are minima of Eq. (6) with n = 3, phi_s = 0.
  */
@@ -555,5 +556,129 @@ int ora_run_leapfrog(const ora_ff* ff, const ora_integ* in, ora_nh* nh, int64_t 
   if (e_out) *e_out = e;
   if (ke_out) *ke_out = ke;
   if (t_out) *t_out = T;
+  return 0;
+}
+
+/* ---------- Section 5 observables ---------- */
+
+static int32_t distance_bin(double r2, double dr, int32_t n_bins) {
+  /* the largest k with (k dr)^2 <= r2; r2 < (n_bins dr)^2 is checked by the caller */
+  int32_t k = (int32_t)(sqrt(r2) / dr);
+  if (k > n_bins - 1) k = n_bins - 1;
+  while (k > 0 && r2 < (k * dr) * (k * dr)) --k;
+  while (k + 1 < n_bins && r2 >= ((k + 1) * dr) * ((k + 1) * dr)) ++k;
+  return k;
+}
+
+static double pair_r2(const double* x, const double* y, const double* z, const double L[3], int64_t i,
+                      int64_t j) {
+  double dx = min_image(x[i] - x[j], L[0]);
+  double dy = min_image(y[i] - y[j], L[1]);
+  double dz = min_image(z[i] - z[j], L[2]);
+  return dx * dx + dy * dy + dz * dz;
+}
+
+int ora_pair_histogram(int64_t n, int32_t chain_len, int32_t excl_depth, const double* x, const double* y,
+                       const double* z, const double L[3], const int32_t* M, double rmax, int32_t n_bins,
+                       uint64_t* counts) {
+  if (n < 0 || chain_len < 1 || excl_depth < 0 || n_bins < 1 || !(rmax > 0) || !counts) return -1;
+  const double dr = rmax / n_bins, rmax2 = (n_bins * dr) * (n_bins * dr);
+  memset(counts, 0, sizeof(uint64_t) * (size_t)n_bins);
+  if (!M) {
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t j = i + 1; j < n; ++j) {
+        if (excluded(i, j, chain_len, excl_depth)) continue;
+        double r2 = pair_r2(x, y, z, L, i, j);
+        if (r2 < rmax2) ++counts[distance_bin(r2, dr, n_bins)];
+      }
+    return 0;
+  }
+  for (int d = 0; d < 3; ++d)
+    if (M[d] < 3 || L[d] / M[d] < rmax) return -2;
+  const int64_t n_cells = (int64_t)M[0] * M[1] * M[2];
+  int32_t* cell = (int32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  int32_t* cnt = (int32_t*)malloc((size_t)n_cells * sizeof(int32_t));
+  int32_t* start = (int32_t*)malloc((size_t)(n_cells + 1) * sizeof(int32_t));
+  int32_t* atoms = (int32_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+  if (!cell || !cnt || !start || !atoms) { free(cell); free(cnt); free(start); free(atoms); return -4; }
+  ora_cell_index(n, x, y, z, L, M, cell);
+  ora_bin(n, cell, n_cells, cnt, start, atoms);
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t c = cell[i];
+    const int32_t kx = c % M[0], ky = (c / M[0]) % M[1], kz = c / (M[0] * M[1]);
+    for (int32_t oz = -1; oz <= 1; ++oz)
+      for (int32_t oy = -1; oy <= 1; ++oy)
+        for (int32_t ox = -1; ox <= 1; ++ox) {
+          int32_t nc = (kx + ox + M[0]) % M[0] + M[0] * ((ky + oy + M[1]) % M[1] + M[1] * ((kz + oz + M[2]) % M[2]));
+          for (int32_t s = start[nc]; s < start[nc + 1]; ++s) {
+            int64_t j = atoms[s];
+            if (j <= i || excluded(i, j, chain_len, excl_depth)) continue;
+            double r2 = pair_r2(x, y, z, L, i, j);
+            if (r2 < rmax2) ++counts[distance_bin(r2, dr, n_bins)];
+          }
+        }
+  }
+  free(cell); free(cnt); free(start); free(atoms);
+  return 0;
+}
+
+int ora_dihedral_stats(int64_t n, int32_t chain_len, const double* x, const double* y, const double* z,
+                       const double L[3], int32_t n_bins, uint64_t* hist, uint64_t classes[3]) {
+  if (n < 0 || chain_len < 4 || n % chain_len || n_bins < 0 || (n_bins > 0 && !hist) || !classes) return -1;
+  ora_ff ff;
+  memset(&ff, 0, sizeof ff);
+  ff.n_dih = 1;
+  if (n_bins > 0) memset(hist, 0, sizeof(uint64_t) * (size_t)n_bins);
+  classes[0] = classes[1] = classes[2] = 0;
+  const double two_pi = 2.0 * M_PI, third = two_pi / 3.0, scale = n_bins / two_pi;
+  for (int64_t p = 0; p < n; ++p) {
+    if (!term_exists(p % chain_len, 4, chain_len)) continue;
+    double s[4][3], f[12], phi;
+    local_sites(x, y, z, L, p, 4, s);
+    ora_dihedral_term(&ff, s[0], s[1], s[2], s[3], f, &phi);
+    if (n_bins > 0) {
+      int32_t k = (int32_t)floor((phi + M_PI) * scale);
+      if (k > n_bins - 1) k = n_bins - 1;
+      if (k < 0) k = 0;
+      ++hist[k];
+    }
+    if (fabs(phi) > third) ++classes[0];
+    else if (phi >= 0) ++classes[1];
+    else ++classes[2];
+  }
+  return 0;
+}
+
+int ora_chain_shape(const ora_ff* ff, int64_t n, int32_t chain_len, const double* x, const double* y,
+                    const double* z, const uint8_t* type, const double L[3], double* out) {
+  if (!ff || n < 0 || chain_len < 1 || n % chain_len || !out) return -1;
+  double* u = (double*)malloc(sizeof(double) * 3 * (size_t)chain_len);
+  if (!u) return -4;
+  for (int64_t c = 0; c < n / chain_len; ++c) {
+    const int64_t a = c * chain_len;
+    u[0] = x[a]; u[1] = y[a]; u[2] = z[a];
+    for (int32_t p = 1; p < chain_len; ++p) {
+      u[3 * p + 0] = u[3 * (p - 1) + 0] + min_image(x[a + p] - x[a + p - 1], L[0]);
+      u[3 * p + 1] = u[3 * (p - 1) + 1] + min_image(y[a + p] - y[a + p - 1], L[1]);
+      u[3 * p + 2] = u[3 * (p - 1) + 2] + min_image(z[a + p] - z[a + p - 1], L[2]);
+    }
+    double msum = 0, cm[3] = {0, 0, 0};
+    for (int32_t p = 0; p < chain_len; ++p) {
+      const double m = ff->mass[type[a + p]];
+      msum += m;
+      for (int q = 0; q < 3; ++q) cm[q] += m * u[3 * p + q];
+    }
+    for (int q = 0; q < 3; ++q) cm[q] /= msum;
+    double rg = 0;
+    for (int32_t p = 0; p < chain_len; ++p) {
+      const double m = ff->mass[type[a + p]];
+      double d2 = 0;
+      for (int q = 0; q < 3; ++q) d2 += (u[3 * p + q] - cm[q]) * (u[3 * p + q] - cm[q]);
+      rg += m * d2;
+    }
+    out[4 * c] = rg / msum;
+    for (int q = 0; q < 3; ++q) out[4 * c + 1 + q] = u[3 * (chain_len - 1) + q] - u[q];
+  }
+  free(u);
   return 0;
 }

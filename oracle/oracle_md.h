@@ -20,7 +20,11 @@
  *   - one leap-frog step with the Nose-Hoover thermostat (Section 3 opening and
  *     Section 3.4: leap-frog, NVT through the Nose-Hoover extended system);
  *   - removal of each box's centre-of-mass velocity (Section 3 opening and the
- *     COM-removal timing of Section 4; translation only, see ora_integ).
+ *     COM-removal timing of Section 4; translation only, see ora_integ);
+ *   - the structural observables of Section 5: the pair-distance histogram behind the
+ *     radial distribution function (Fig. 10), the dihedral (conformation) distribution
+ *     and trans fraction (Figs. 9, 15), and per-chain radius of gyration and end-to-end
+ *     vector (Figs. 8, 12).
  *
  * Units: Angstrom, fs, g/mol, kcal/mol, K.  Every array is caller-owned host
  * memory; coordinates are structure-of-arrays.  Functions return 0 on success and
@@ -158,6 +162,33 @@ int ora_run_leapfrog(const ora_ff* ff, const ora_integ* in, ora_nh* nh, int64_t 
                      double* x, double* y, double* z, double* vx, double* vy, double* vz, double* fx,
                      double* fy, double* fz, const uint8_t* type, const double L[3], const int32_t M[3],
                      int32_t R, int32_t n_steps, ora_energy* e_out, double* ke_out, double* t_out);
+
+/* Pair-distance histogram (Section 5, Fig. 10): every unordered pair i < j that the force
+   field does not exclude (excluded: same chain, at most excl_depth bonds apart), with the
+   minimum-image distance r < rmax, counted in bin k = floor(r / dr), dr = rmax / n_bins.
+   The bin is decided on r^2 = dx*dx + dy*dy + dz*dz (FP64, in that order, no fused
+   multiply-add) against the squared edges (k * dr)^2, so no square root takes part in it.
+   M == NULL: all pairs by brute force.  Otherwise the grid search over the 27 cells around
+   each atom's cell (M[d] >= 3, L[d] / M[d] >= rmax; positions wrapped).  counts[n_bins]
+   are written. */
+int ora_pair_histogram(int64_t n, int32_t chain_len, int32_t excl_depth, const double* x, const double* y,
+                       const double* z, const double L[3], const int32_t* M, double rmax, int32_t n_bins,
+                       uint64_t* counts);
+
+/* Dihedral statistics (Section 5, Figs. 9 and 15): the IUPAC angle phi in (-pi, pi] of every
+   dihedral of every chain (bonds minimum-imaged; the angle as ora_dihedral_term computes
+   it).  hist[k] counts k = floor((phi + pi) * (n_bins / (2 pi))), clamped to n_bins - 1
+   (n_bins may be 0: no histogram); classes[0] = trans (|phi| > 2 pi / 3), classes[1] =
+   gauche+ (0 <= phi <= 2 pi / 3), classes[2] = gauche- (-2 pi / 3 <= phi < 0). */
+int ora_dihedral_stats(int64_t n, int32_t chain_len, const double* x, const double* y, const double* z,
+                       const double L[3], int32_t n_bins, uint64_t* hist, uint64_t classes[3]);
+
+/* Chain shape (Section 5, Figs. 8 and 12): each chain unwrapped link by link from its first
+   atom (u_0 = x_0, u_{p+1} = u_p + minimum image of x_{p+1} - x_p), the mass-weighted
+   radius of gyration Rg^2 = sum m |u - u_cm|^2 / sum m with u_cm = sum m u / sum m, and the
+   end-to-end vector u_last - u_first.  out[4 c] = Rg^2 (A^2), out[4 c + 1..3] = R_ee (A). */
+int ora_chain_shape(const ora_ff* ff, int64_t n, int32_t chain_len, const double* x, const double* y,
+                    const double* z, const uint8_t* type, const double L[3], double* out);
 
 #ifdef __cplusplus
 }
