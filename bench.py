@@ -9,7 +9,8 @@ at the end of the timed run), per-phase kernel times, the roofline position of t
 Lennard-Jones kernel, the FP64 CPU oracle timed on a bounded sample of the workload, and
 two more forms of the step from the end state of the timed run: Verlet neighbour lists
 (skin 1 A, rebuilt every 10 steps) and the paper's leap-frog + Nose-Hoover integrator with
-the centre-of-mass velocity removed every step.
+the centre-of-mass velocity removed every step; and the time of one Section 5 observables
+call (pair-distance histogram, dihedral statistics, chain shape).
 
 ``--workload`` selects one of the other presets instead (their own JSON line, same keys):
 melt3M_mixed (NVT throughput, then the NVE energy drift over 1,000 steps), ensemble64_mixed
@@ -117,6 +118,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-nlist", action="store_true", help="skip the neighbour-list form")
     ap.add_argument("--no-leapfrog", action="store_true", help="skip the leap-frog + Nose-Hoover form")
+    ap.add_argument("--no-observables", action="store_true", help="skip the Section 5 observables")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first copy a device buffer of this many MiB (HBM counter calibration)")
     ap.add_argument("--workload", default="melt300k_mixed",
@@ -184,6 +186,28 @@ def main():
     pos_prof, vel_prof = s.state()
     f_end = s.forces()
     f_end_lj = s.forces(lj_only=True)
+
+    # Section 5 observables of the end-of-run state (pair-distance histogram, dihedral
+    # statistics, chain shape), one md_observables call including the copies to the host
+    observables = None
+    if not args.no_observables:
+        try:
+            s.observables(rdf_bins=210, rdf_rmax=10.5, dih_bins=72)
+            reps = 5
+            a = time.perf_counter()
+            for _ in range(reps):
+                o = s.observables(rdf_bins=210, rdf_rmax=10.5, dih_bins=72)
+            b_ = time.perf_counter()
+            cls = o["dihedral_classes"][0].astype(float)
+            observables = {"ms_per_call": 1e3 * (b_ - a) / reps, "rdf_bins": 210, "rdf_rmax_A": 10.5,
+                           "dih_bins": 72, "pairs_counted": int(o["pair_counts"][0].sum()),
+                           "trans_fraction": float(cls[0] / cls.sum()),
+                           "mean_rg2_A2": float(o["chain_shape"][:, 0].mean()),
+                           "mean_ree2_A2": float((o["chain_shape"][:, 1:] ** 2).sum(axis=1).mean())}
+            log("observables: %.3f ms per call, trans fraction %.4f, <Rg^2> %.1f A^2"
+                % (observables["ms_per_call"], observables["trans_fraction"], observables["mean_rg2_A2"]))
+        except Exception as exc:
+            log("observables failed: %r" % (exc,))
     s.close()
 
     # ---- the paper's force path beside it: Verlet lists (skin 1 A) rebuilt every 10 steps,
@@ -339,6 +363,7 @@ def main():
         "cpu_baseline_1thread": cpu1,
         "nlist_form": nlist,
         "leapfrog_nh_form": leapfrog,
+        "observables": observables,
     }
     print(json.dumps(out), flush=True)
 

@@ -236,6 +236,33 @@ md_status md_forces_lj(md_ctx* ctx, const void** f, int32_t* is_fp32);
 /* The stencil radius and LJ kernel in use (what the autotuner chose, if asked). */
 md_status md_tuning(const md_ctx* ctx, int32_t* cell_div, int32_t* lj_kernel);
 
+/* Structural observables of Section 5 (Figs. 8-10, 12, 15). */
+#define MD_OBS_MAX_BINS 2048
+typedef struct {
+  int32_t rdf_bins;    /* pair-distance bins over [0, rdf_rmax), 1..MD_OBS_MAX_BINS */
+  double rdf_rmax;     /* A, 0 < rdf_rmax <= rc */
+  int32_t dih_bins;    /* dihedral-angle bins over (-180, 180] deg, 0..MD_OBS_MAX_BINS - 3 */
+} md_obs_config;
+
+/* Observables of the current positions, per box, into caller-owned device buffers (any of
+   the three may be null to skip that part):
+   pair_counts     uint64 [n_boxes * rdf_bins]: unordered pairs the force field does not
+                   exclude with minimum-image distance r < rdf_rmax, in bin floor(r / dr),
+                   dr = rdf_rmax / rdf_bins.  The bin is decided in FP64 on r^2 against the
+                   squared edges (k dr)^2, so the counts are exact.  g(r) of bin k is
+                   counts[k] / (N (N - 1) / 2 * shell volume / V) (excluded pairs not removed
+                   from the normalisation).
+   dihedral_counts uint64 [n_boxes * (dih_bins + 3)]: per box, the histogram of the IUPAC
+                   dihedral angle phi in (-pi, pi], bin floor((phi + pi) dih_bins / (2 pi)),
+                   then the numbers of trans (|phi| > 120 deg), gauche+ (0 <= phi <= 120 deg)
+                   and gauche- dihedrals.
+   chain_shape     double [n_chains_total * 4]: per chain (box by box), the mass-weighted
+                   R_g^2 (A^2) of the chain unwrapped bond by bond, and the end-to-end vector.
+   Uses the cell lists of the last rebuild (current after md_step; in neighbour-list mode
+   those of the last list build, which still cover every pair within rc).  Enqueues only. */
+md_status md_observables(md_ctx* ctx, const md_obs_config* cfg, uint64_t* pair_counts,
+                         uint64_t* dihedral_counts, double* chain_shape);
+
 /* Frees the host-side context and its graph; device buffers stay with the caller. */
 md_status md_destroy(md_ctx* ctx);
 

@@ -14,7 +14,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["md_api.hip", "md_kernels.hip", "md_lj.hip"]
+SOURCES = ["md_api.hip", "md_kernels.hip", "md_lj.hip", "md_obs.hip"]
 HEADERS = ["md_internal.h"]
 LIB = os.path.join(HERE, "libmd_gfx950.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -244,6 +244,7 @@ size_t carve(const Plan& p, char* base, Views* v) {
   t.thermo = (double*)take(8 * kThermo * (size_t)p.n_boxes);
   t.energy = (double*)take(8 * kEnergySlots * (size_t)p.n_boxes);
   t.err = (int32_t*)take(4);
+  t.obs_part = (uint32_t*)take(4 * (size_t)kObsBlocks * kMaxObsBins);
   if (p.nl_cap) {
     t.nl_cap = p.nl_cap;
     t.n_cell_blocks = p.n_cell_blocks;
@@ -782,6 +783,28 @@ md_status md_tuning(const md_ctx* c, int32_t* cell_div, int32_t* lj_kernel) {
   *cell_div = c->R;
   *lj_kernel = c->lj_kernel;
   return MD_OK;
+}
+
+md_status md_observables(md_ctx* c, const md_obs_config* o, uint64_t* pairs, uint64_t* dih, double* shape) {
+  static_assert(kMaxObsBins == MD_OBS_MAX_BINS, "observable bins");
+  if (!c || !o) return MD_ERR_ARG;
+  if (c->failed) return MD_ERR_STATE;
+  if (pairs && (o->rdf_bins < 1 || o->rdf_bins > kMaxObsBins || !(o->rdf_rmax > 0.0) || !(o->rdf_rmax <= c->ff.rc)))
+    return fail(c, MD_ERR_ARG, "rdf_bins must be 1..MD_OBS_MAX_BINS and 0 < rdf_rmax <= rc");
+  if (dih && (o->dih_bins < 0 || o->dih_bins > kMaxObsBins - 3))
+    return fail(c, MD_ERR_ARG, "dih_bins must be 0..MD_OBS_MAX_BINS - 3");
+  const double dr = pairs ? o->rdf_rmax / o->rdf_bins : 0.0;
+  for (int b = 0; b < c->n_boxes; ++b) {
+    const int64_t n = (int64_t)c->n_chains[b] * c->chain_len;
+    if (pairs)
+      launch_obs_pairs(c->v, b, n, c->chain_len, c->ff.excl_depth, dr, o->rdf_bins,
+                       (unsigned long long*)pairs + (int64_t)b * o->rdf_bins, c->stream);
+    if (dih)
+      launch_obs_dihedrals(c->v, b, n, c->chain_len, o->dih_bins,
+                           (unsigned long long*)dih + (int64_t)b * (o->dih_bins + 3), c->stream);
+    if (shape) launch_obs_chains(c->v, c->ffd, b, c->n_chains[b], c->chain_len, shape, c->stream);
+  }
+  return check_launch(c, "observables");
 }
 
 md_status md_destroy(md_ctx* c) {

@@ -118,11 +118,14 @@ struct Views {
   void* pay_cur;         // [N] payload refreshed every step between builds
   double nl_rl2;         // (rc + skin)^2
   double nl_half_skin2;  // (skin / 2)^2
+  uint32_t* obs_part;    // [kObsBlocks * kMaxObsBins] block partials of the observables
 };
 
 enum ErrBits : int32_t { kErrNonFinite = 1, kErrNlMoved = 2, kErrNlFull = 4 };
 
 constexpr int kBdParts = 8;      // block partials of the bonded kernel
+constexpr int kMaxObsBins = 2048;  // histogram bins of one observable (md.h: MD_OBS_MAX_BINS)
+constexpr int kObsBlocks = 512;    // work-groups of an observable kernel (grid-stride)
 constexpr int kEnergySlots = 10; // per box: E_lj, E_lj_shifted, E_b, E_a, E_d, KE, T, W, xi, E_thermostat
 
 // Integrator state per box.  The velocity update of the next step is
@@ -161,6 +164,14 @@ void launch_reduce(const Views& v, bool energy, bool update, const StepOpts& o, 
 void launch_finalize(const Views& v, const StepOpts& o, hipStream_t s);
 // neighbour-list mode: update + displacement check + payload refresh between builds
 void launch_nl_integrate(const Views& v, const StepOpts& o, const FFDev& ff, bool fp32_force, hipStream_t s);
+
+// ---- launchers (md_obs.hip): Section 5 observables of box b ----
+void launch_obs_pairs(const Views& v, int b, int64_t n_atoms, int chain_len, int excl, double dr, int n_bins,
+                      unsigned long long* out, hipStream_t s);
+void launch_obs_dihedrals(const Views& v, int b, int64_t n_atoms, int chain_len, int n_bins,
+                          unsigned long long* out, hipStream_t s);
+void launch_obs_chains(const Views& v, const FFDev& ff, int b, int64_t n_chains, int chain_len, double* out,
+                       hipStream_t s);
 
 constexpr int kTileHomesMixed = 8;   // home atoms per pass of a mixed cell-tile wave
 

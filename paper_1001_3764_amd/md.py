@@ -47,6 +47,13 @@ class md_energy(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class md_obs_config(ctypes.Structure):
+    _fields_ = [("rdf_bins", _I32), ("rdf_rmax", _D), ("dih_bins", _I32)]
+
+
+MD_OBS_MAX_BINS = 2048
+
+
 class MDError(RuntimeError):
     def __init__(self, status, what, detail=""):
         self.status = status
@@ -80,6 +87,7 @@ def load():
         "md_forces_lj": (S, [_P, ctypes.POINTER(_P), ctypes.POINTER(_I32)]),
         "md_tuning": (S, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
         "md_destroy": (S, [_P]),
+        "md_observables": (S, [_P, _P, _P, _P, _P]),
         "md_status_string": (ctypes.c_char_p, [S]),
         "md_last_error": (ctypes.c_char_p, [_P]),
     }
@@ -218,6 +226,16 @@ def md_tuning(ctx):
     return r.value, k.value
 
 
+def rdf_from_counts(counts, n_atoms, box, rmax):
+    """g(r) at the bin centres from md_observables' pair counts of one box: counts over the
+    ideal-gas expectation N (N - 1) / 2 * shell volume / V."""
+    counts = np.asarray(counts, dtype=np.float64)
+    edges = np.arange(counts.size + 1) * (rmax / counts.size)
+    shell = 4.0 / 3.0 * np.pi * (edges[1:] ** 3 - edges[:-1] ** 3)
+    ideal = n_atoms * (n_atoms - 1) / 2.0 * shell / float(np.prod(box))
+    return 0.5 * (edges[1:] + edges[:-1]), counts / ideal
+
+
 def md_destroy(ctx):
     _check(load().md_destroy(ctx), "md_destroy")
 
@@ -275,6 +293,31 @@ class MDSystem:
 
     def grid(self, box=0):
         return md_grid(self.ctx, box)
+
+    def observables(self, rdf_bins=105, rdf_rmax=10.5, dih_bins=72, pairs=True, dihedrals=True, shape=True):
+        """Section 5 observables of the current positions (md_observables): a dict of numpy
+        arrays pair_counts [n_boxes, rdf_bins], dihedral_hist [n_boxes, dih_bins],
+        dihedral_classes [n_boxes, 3] (trans, gauche+, gauche-) and chain_shape
+        [n_chains, 4] (R_g^2, end-to-end vector)."""
+        nb, nch = self.n_boxes, int(self.cfg.n_chains.sum())
+        cfg = md_obs_config(rdf_bins=int(rdf_bins), rdf_rmax=float(rdf_rmax), dih_bins=int(dih_bins))
+        # never empty, so a bad bin count reaches the library's own check rather than a null pointer
+        pc = torch.zeros(max(nb * rdf_bins, 1), dtype=torch.int64, device=self.device)
+        dc = torch.zeros(max(nb * (dih_bins + 3), 1), dtype=torch.int64, device=self.device)
+        cs = torch.zeros(nch * 4, dtype=torch.float64, device=self.device)
+        _check(load().md_observables(self.ctx, ctypes.byref(cfg), pc.data_ptr() if pairs else None,
+                                     dc.data_ptr() if dihedrals else None, cs.data_ptr() if shape else None),
+               "md_observables", self.ctx)
+        torch.cuda.synchronize(self.device)
+        out = {}
+        if pairs:
+            out["pair_counts"] = pc.cpu().numpy().view(np.uint64).reshape(nb, rdf_bins)
+        if dihedrals:
+            d = dc.cpu().numpy().view(np.uint64).reshape(nb, dih_bins + 3)
+            out["dihedral_hist"], out["dihedral_classes"] = d[:, :dih_bins], d[:, dih_bins:]
+        if shape:
+            out["chain_shape"] = cs.cpu().numpy().reshape(nch, 4)
+        return out
 
     # --- device views copied to host ---
     def _ws_view(self, ptr, count, dtype):

@@ -40,7 +40,8 @@ def test_every_declared_function_is_exported(md):
 
 def test_struct_layouts_match_the_header(md, tmp_path):
     """sizeof and offsetof of every field, from a C program compiled against md.h."""
-    structs = {"md_forcefield": md.md_forcefield, "md_config": md.md_config, "md_energy": md.md_energy}
+    structs = {"md_forcefield": md.md_forcefield, "md_config": md.md_config, "md_energy": md.md_energy,
+               "md_obs_config": md.md_obs_config}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "md.h"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append('printf("%s sizeof %%zu\\n", sizeof(%s));' % (name, name))
