@@ -208,6 +208,55 @@ def test_pairs_at_the_cutoff(ff, precision, R, kernel):
     assert np.max(np.abs(flj - fo)) < 0.02 * abs(f_rc)
 
 
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+@pytest.mark.parametrize("R,kernel,nl", [(1, 2, False), (2, 2, False), (2, 3, False), (2, 1, False), (1, 0, True)])
+def test_many_pairs_at_the_cutoff(ff, precision, R, kernel, nl):
+    """One atom with 100 partners on a sphere of radius rc (1 + delta), |delta| <= 4e-7: more
+    band pairs than the cell tile's queue holds (64), spread over more than its 8 recorded
+    steps, so the group falls back to walking all of its candidates again.  The pair set must
+    still be the FP64 one."""
+    rc = ff["rc"]
+    rng = np.random.default_rng(12)
+    m = 100
+    g = (1 + 5 ** 0.5) / 2
+    t = np.arange(m) + 0.5
+    u = np.stack([np.cos(2 * np.pi * t / g) * np.sqrt(1 - (1 - 2 * t / m) ** 2),
+                  np.sin(2 * np.pi * t / g) * np.sqrt(1 - (1 - 2 * t / m) ** 2), 1 - 2 * t / m])
+    delta = rng.uniform(1e-9, 4e-7, m) * np.where(np.arange(m) % 2 == 0, 1.0, -1.0)
+    centre = np.array([20.0, 20.0, 20.0])
+    sphere = centre[:, None] + rc * (1 + delta) * u
+    # chains of 4: the centre and three atoms far from everything; then the sphere, 4 at a time
+    far = np.array([[3.0, 3.0, 3.0], [3.0, 7.0, 3.0], [7.0, 3.0, 3.0]]).T
+    pos = np.concatenate([centre[:, None], far, sphere], axis=1)
+    box = np.array([40.0, 40.0, 40.0])
+    types = np.zeros(pos.shape[1], dtype=np.uint8)
+    fo, _ = O.lj_brute(ff, pos, types, box, 4)
+    d = sphere - centre[:, None]
+    assert np.array_equal(np.sum(d * d, axis=0) < rc * rc, delta < 0)   # the oracle's own pair set
+    from paper_1001_3764_amd.md import MDSystem
+    print("many cutoff pairs: precision=%s R=%d kernel=%d nl=%s" % (precision, R, kernel, nl), flush=True)
+    kw = dict(nl_skin=1.0, nl_every=5) if nl else dict(lj_kernel=kernel)
+    s = MDSystem(ff, [pos.shape[1] // 4], box[None, :], [0.0], pos, np.zeros_like(pos), types, chain_len=4,
+                 precision=precision, cell_div=R, **kw)
+    if nl:
+        # the list holds 1.5x the mean neighbour count of this sparse box plus 79 (80 entries):
+        # the centre's 100 partners overflow it, which is reported, not silently truncated
+        from paper_1001_3764_amd.md import MD_ERR_NLIST, MDError
+        with pytest.raises(MDError) as ex:
+            s.energies()
+        assert ex.value.status == MD_ERR_NLIST
+        s.close()
+        return
+    flj = s.forces(lj_only=True)
+    e = s.energies()[0]
+    s.close()
+    s6 = ff["sigma"][0] ** 6
+    f_rc = 4 * ff["epsilon"][0] * (12 * s6 * s6 / rc ** 13 - 6 * s6 / rc ** 7)
+    assert np.max(np.abs(flj - fo)) < 0.02 * abs(f_rc)
+    _, eo = O.lj_brute(ff, pos, types, box, 4)
+    assert e["e_lj"] == pytest.approx(eo["e_lj"], rel=1e-6)
+
+
 def _ensemble(n_boxes=3):
     melts = [make_melt(c, density=0.80, T=300.0 + 50 * k, seed_melt=900 + k, seed_vel=950 + k, jitter=0.05)
              for k, c in enumerate((4, 11, 7)[:n_boxes])]
