@@ -177,9 +177,9 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_tiles(const int32_t* __rest
   if (threadIdx.x == 0) tiles[blockIdx.x] = total;
 }
 
-// Tile b's offset is the sum of tiles[0..b) (each block sums them itself: no separate pass
-// over the tile totals), then the tile's own counts are scanned and cleared for the next
-// binning.
+// Tile b's offset is the sum of the tile totals tiles[0..b) (each block sums them itself: no
+// separate pass over the tile totals), then the tile's own counts are scanned (k_scatter
+// clears them for the next binning).
 __global__ __launch_bounds__(kScanBlock) void k_scan(int32_t* __restrict__ cnt, int64_t C,
                                                     const int32_t* __restrict__ tiles,
                                                     int32_t* __restrict__ cell_start) {
@@ -198,16 +198,16 @@ __global__ __launch_bounds__(kScanBlock) void k_scan(int32_t* __restrict__ cnt, 
   int total;
   int ex = block_exclusive_scan(s, sh, &total) + offset;
   for (int k = 0; k < kScanItems; ++k) {
-    if (base + k < C) {
-      cell_start[base + k] = ex;
-      cnt[base + k] = 0;   // ready for the next count
-    }
+    if (base + k < C) cell_start[base + k] = ex;
     ex += vals[k];
   }
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) cell_start[C] = offset + total;
 }
 
 __global__ __launch_bounds__(kAtomBlock) void k_scatter(Views v) {
+  // the scan has read the counts: clear them for the next binning
+  for (int64_t c = (int64_t)blockIdx.x * kAtomBlock + threadIdx.x; c < v.C; c += (int64_t)gridDim.x * kAtomBlock)
+    v.cnt[c] = 0;
   const int b = v.blk_box[blockIdx.x];
   const BoxDev& B = v.boxes[b];
   const int local = ((int)blockIdx.x - B.blk_off) * kAtomBlock + (int)threadIdx.x;
@@ -564,98 +564,108 @@ __global__ __launch_bounds__(kAtomBlock) void k_bonded(Views v, FFDev ff, double
   }
 }
 
-// One block per box: sum the block partials of the box in a fixed order.
-__device__ dd block_sum(const dd* part, int stride, int k, int first, int count, dd* sh) {
-  dd s{0.0, 0.0};
-  for (int t = threadIdx.x; t < count; t += blockDim.x) s = dd_add(s, part[(int64_t)(first + t) * stride + k]);
-  for (int off = 32; off > 0; off >>= 1) {
-    dd o{__shfl_xor(s.hi, off), __shfl_xor(s.lo, off)};
-    s = dd_add(s, o);
+// Sums NV double-double values over the block in a fixed order (each thread's own values,
+// then a butterfly over the wave, then the waves in order); every thread gets the sums.
+template <int NV>
+__device__ void block_sums(dd (&s)[NV], dd (*sh)[NV]) {
+  for (int k = 0; k < NV; ++k)
+    for (int off = 32; off > 0; off >>= 1) {
+      dd o{__shfl_xor(s[k].hi, off), __shfl_xor(s[k].lo, off)};
+      s[k] = dd_add(s[k], o);
+    }
+  if (lane() == 0)
+    for (int k = 0; k < NV; ++k) sh[threadIdx.x >> 6][k] = s[k];
+  __syncthreads();
+  for (int k = 0; k < NV; ++k) {
+    dd r = sh[0][k];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = dd_add(r, sh[w][k]);
+    s[k] = r;
   }
-  if (lane() == 0) sh[threadIdx.x >> 6] = s;
   __syncthreads();
-  dd r = sh[0];
-  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = dd_add(r, sh[w]);
-  __syncthreads();
-  return r;
 }
 
-// One block per box: the box's energies, kinetic energy and temperature; with update, the
-// integrator state the next step applies:
+// One block per box: the box's energies, kinetic energy and temperature, all partials read
+// in one pass; with update, the integrator state the next step applies:
 //   velocity Verlet: the Berendsen factor lambda = sqrt(1 + dt/tau (T0/T - 1));
 //   leap-frog: xi' = xi + dt omega^2 (T/T0 - 1), omega = 2 pi / tau, eta += dt (xi + xi')/2,
 //              and the kick factors 1 - dt xi'/2 and 1 / (1 + dt xi'/2);
 //   COM removal: u = P / M, and the kinetic energy of the motion relative to it,
 //              KE - |P|^2 / (2 M).
-__global__ __launch_bounds__(256) void k_reduce(Views v, int energy, int update, StepOpts o) {
-  __shared__ dd sh[4];
+// Bonded partials: 0 E_b, 1 E_a, 2 E_d, 3 W_b, 4 KE, 5..7 momentum; LJ: E, E_shifted, W.
+// ENERGY: the energies and virial too; COM (with update): the momentum and u.
+template <bool ENERGY, bool COM>
+__global__ __launch_bounds__(256) void k_reduce(Views v, int update, StepOpts o) {
+  // q: KE, [momentum xyz], [E_b E_a E_d W_b E_lj E_lj_shifted W_lj]
+  constexpr int iP = 1, iE = COM ? 4 : 1, NV = iE + (ENERGY ? 7 : 0);
+  __shared__ dd sh[4][NV];
   const int b = blockIdx.x;
   const BoxDev& B = v.boxes[b];
   const int first = B.blk_off;
   const int count = (B.n_atoms + kAtomBlock - 1) / kAtomBlock;
-  const dd ke = block_sum(v.part_bd, kBdParts, 4, first, count, sh);
-  double KE = ke.hi + ke.lo;
-  const bool com = update && o.remove_com;
+  dd q[NV];
+  for (int k = 0; k < NV; ++k) q[k] = dd{0.0, 0.0};
+  for (int t = threadIdx.x; t < count; t += blockDim.x) {
+    const dd* p = v.part_bd + (int64_t)(first + t) * kBdParts;
+    q[0] = dd_add(q[0], p[4]);
+    if (COM)
+      for (int k = 0; k < 3; ++k) q[iP + k] = dd_add(q[iP + k], p[5 + k]);
+    if (ENERGY)
+      for (int k = 0; k < 4; ++k) q[iE + k] = dd_add(q[iE + k], p[k]);
+  }
+  if (ENERGY) {
+    const int lfirst = B.lj_blk_off;
+    const int lcount = (b + 1 < v.n_boxes ? v.boxes[b + 1].lj_blk_off : v.n_lj_blocks) - lfirst;
+    for (int t = threadIdx.x; t < lcount; t += blockDim.x)
+      for (int k = 0; k < 3; ++k) q[iE + 4 + k] = dd_add(q[iE + 4 + k], v.part_lj[(int64_t)(lfirst + t) * 3 + k]);
+  }
+  block_sums<NV>(q, sh);
+  double KE = q[0].hi + q[0].lo;
   double u[3] = {0.0, 0.0, 0.0};
-  if (com) {
+  if (COM) {
     double p[3];
     for (int k = 0; k < 3; ++k) {
-      const dd s = block_sum(v.part_bd, kBdParts, 5 + k, first, count, sh);
-      p[k] = s.hi + s.lo;
+      p[k] = q[iP + k].hi + q[iP + k].lo;
       u[k] = p[k] * B.inv_mass;
     }
     KE -= 0.5 * (p[0] * u[0] + p[1] * u[1] + p[2] * u[2]) / kAccUnit;
   }
   const double T = 2.0 * KE / (B.dof * kRgas);
   double* out = v.energy + (int64_t)b * kEnergySlots;
-  if (energy) {
-    const int lfirst = B.lj_blk_off;
-    const int lcount = (b + 1 < v.n_boxes ? v.boxes[b + 1].lj_blk_off : v.n_lj_blocks) - lfirst;
-    dd q[7];
-    q[0] = block_sum(v.part_lj, 3, 0, lfirst, lcount, sh);
-    q[1] = block_sum(v.part_lj, 3, 1, lfirst, lcount, sh);
-    q[2] = block_sum(v.part_bd, kBdParts, 0, first, count, sh);
-    q[3] = block_sum(v.part_bd, kBdParts, 1, first, count, sh);
-    q[4] = block_sum(v.part_bd, kBdParts, 2, first, count, sh);
-    q[5] = block_sum(v.part_lj, 3, 2, lfirst, lcount, sh);
-    q[6] = block_sum(v.part_bd, kBdParts, 3, first, count, sh);
-    if (threadIdx.x == 0) {
-      out[0] = q[0].hi + q[0].lo;
-      out[1] = q[1].hi + q[1].lo;
-      out[2] = q[2].hi + q[2].lo;
-      out[3] = q[3].hi + q[3].lo;
-      out[4] = q[4].hi + q[4].lo;
-      const dd w = dd_add(q[5], q[6]);
-      out[7] = w.hi + w.lo;
-    }
+  if (threadIdx.x != 0) return;
+  if (ENERGY) {
+    out[0] = q[iE + 4].hi + q[iE + 4].lo;
+    out[1] = q[iE + 5].hi + q[iE + 5].lo;
+    out[2] = q[iE].hi + q[iE].lo;
+    out[3] = q[iE + 1].hi + q[iE + 1].lo;
+    out[4] = q[iE + 2].hi + q[iE + 2].lo;
+    const dd w = dd_add(q[iE + 6], q[iE + 3]);
+    out[7] = w.hi + w.lo;
   }
-  if (threadIdx.x == 0) {
-    out[5] = KE;
-    out[6] = T;
-    double* th = v.thermo + (int64_t)b * kThermo;
-    const double two_pi = 6.283185307179586;
-    const double w2 = (two_pi / o.tau) * (two_pi / o.tau);
-    const bool lf = o.integrator == kLeapfrogNoseHoover;
-    if (update) {
-      if (!lf) {
-        double lam = 1.0;
-        if (B.T0 > 0.0 && T > 0.0) lam = sqrt(1.0 + o.dt / o.tau * (B.T0 / T - 1.0));
-        th[kThPre] = lam;
-      } else if (B.T0 > 0.0) {
-        const double xi = th[kThXi];
-        const double xn = xi + o.dt * w2 * (T / B.T0 - 1.0);
-        th[kThEta] += 0.5 * o.dt * (xi + xn);
-        th[kThXi] = xn;
-        th[kThPre] = 1.0 - 0.5 * o.dt * xn;
-        th[kThPost] = 1.0 / (1.0 + 0.5 * o.dt * xn);
-      }
-      if (com)
-        for (int k = 0; k < 3; ++k) th[kThU + k] = u[k];
+  out[5] = KE;
+  out[6] = T;
+  double* th = v.thermo + (int64_t)b * kThermo;
+  const double two_pi = 6.283185307179586;
+  const double w2 = (two_pi / o.tau) * (two_pi / o.tau);
+  const bool lf = o.integrator == kLeapfrogNoseHoover;
+  if (update) {
+    if (!lf) {
+      double lam = 1.0;
+      if (B.T0 > 0.0 && T > 0.0) lam = sqrt(1.0 + o.dt / o.tau * (B.T0 / T - 1.0));
+      th[kThPre] = lam;
+    } else if (B.T0 > 0.0) {
+      const double xi = th[kThXi];
+      const double xn = xi + o.dt * w2 * (T / B.T0 - 1.0);
+      th[kThEta] += 0.5 * o.dt * (xi + xn);
+      th[kThXi] = xn;
+      th[kThPre] = 1.0 - 0.5 * o.dt * xn;
+      th[kThPost] = 1.0 / (1.0 + 0.5 * o.dt * xn);
     }
-    const double xi = th[kThXi];
-    out[8] = xi;
-    out[9] = lf && B.T0 > 0.0 ? B.dof * kRgas * B.T0 * (xi * xi / (2.0 * w2) + th[kThEta]) : 0.0;
+    if (COM)
+      for (int k = 0; k < 3; ++k) th[kThU + k] = u[k];
   }
+  const double xi = th[kThXi];
+  out[8] = xi;
+  out[9] = lf && B.T0 > 0.0 ? B.dof * kRgas * B.T0 * (xi * xi / (2.0 * w2) + th[kThEta]) : 0.0;
 }
 
 // Applies the pending Berendsen factor (velocity Verlet) and COM velocity to v.
@@ -725,9 +735,9 @@ void launch_bin_count(const Views& v, bool kick, const StepOpts& o, const FFDev&
 static int scan_tiles(const Views& v) { return (int)((v.C + kScanTile - 1) / kScanTile); }
 
 void launch_scan(const Views& v, hipStream_t s) {
-  hipLaunchKernelGGL(k_scan_tiles, dim3(scan_tiles(v)), dim3(kScanBlock), 0, s, v.cnt, v.C, v.scan_tiles);
-  hipLaunchKernelGGL(k_scan, dim3(scan_tiles(v)), dim3(kScanBlock), 0, s, v.cnt, v.C, v.scan_tiles,
-                     v.cell_start);
+  const int n = scan_tiles(v);
+  hipLaunchKernelGGL(k_scan_tiles, dim3(n), dim3(kScanBlock), 0, s, v.cnt, v.C, v.scan_tiles);
+  hipLaunchKernelGGL(k_scan, dim3(n), dim3(kScanBlock), 0, s, v.cnt, v.C, v.scan_tiles, v.cell_start);
 }
 
 void launch_scatter(const Views& v, hipStream_t s) {
@@ -767,7 +777,15 @@ void launch_bonded(const Views& v, const FFDev& ff, bool fp32, BondedMode mode, 
 }
 
 void launch_reduce(const Views& v, bool energy, bool update, const StepOpts& o, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3(v.n_boxes), dim3(256), 0, s, v, energy ? 1 : 0, update ? 1 : 0, o);
+  const int u = update ? 1 : 0;
+  const bool com = update && o.remove_com;
+  if (energy) {
+    if (com) hipLaunchKernelGGL((k_reduce<true, true>), dim3(v.n_boxes), dim3(256), 0, s, v, u, o);
+    else hipLaunchKernelGGL((k_reduce<true, false>), dim3(v.n_boxes), dim3(256), 0, s, v, u, o);
+  } else {
+    if (com) hipLaunchKernelGGL((k_reduce<false, true>), dim3(v.n_boxes), dim3(256), 0, s, v, u, o);
+    else hipLaunchKernelGGL((k_reduce<false, false>), dim3(v.n_boxes), dim3(256), 0, s, v, u, o);
+  }
 }
 
 void launch_nl_integrate(const Views& v, const StepOpts& o, const FFDev& ff, bool fp32_force, hipStream_t s) {
