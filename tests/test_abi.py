@@ -104,6 +104,10 @@ def test_workspace_bytes_and_validation(md, ff):
     ]
     for kw in bad:
         assert workspace(md, ff, config(md, **kw))[0] == md.MD_ERR_ARG, kw
+    # 2^25 atoms is the limit (the LJ candidate list packs sorted indices in 25 bits)
+    big = (1 << 25) // 300 + 1
+    assert workspace(md, ff, config(md, n_chains=(big,), box=((1000.0, 1000.0, 1000.0),)))[0] == md.MD_ERR_ARG
+    assert workspace(md, ff, config(md, n_chains=(big - 1,), box=((1000.0, 1000.0, 1000.0),)))[0] == md.MD_OK
     cfg = config(md)
     cfg.c.remove_com = 2
     assert workspace(md, ff, cfg)[0] == md.MD_ERR_ARG

@@ -156,6 +156,21 @@ def test_melt3M_bins_and_sampled_forces(ff):
     s.close()
 
 
+def test_melt30M_bins_and_sampled_forces(ff):
+    """The largest workload, 30,000,000 atoms (close to the 2^25 limit): bins bit-exact, every
+    bonded force, 1,000 sampled LJ forces, in the benchmark's launch configuration."""
+    O.set_threads(threads())
+    melt = build_melts(WORKLOADS["melt30M_mixed"], threads())[0]
+    s = system(ff, [melt], WORKLOADS["melt30M_mixed"], cell_div=0, lj_kernel=0, use_graph=True)
+    print("tuned (R, kernel) =", s.tuning(), flush=True)
+    check_bins(s, melt)
+    check_sampled_forces(ff, s, melt, 1000, 29)
+    s.step(2)
+    e = s.energies()[0]
+    assert np.isfinite(e["temperature"]) and e["step"] == 2
+    s.close()
+
+
 def test_ensemble64_smallest_box(ff):
     """The 64-box ensemble (about 4.3M atoms) in one launch sequence: every box's bins, and
     the smallest box's forces, energies and first 100 steps against the oracle."""
