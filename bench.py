@@ -357,6 +357,10 @@ def main():
         "plain_fp64_gpu": plain,
         "speedup_vs_plain_fp64": (value / plain["value"]) if plain else None,
         "phases_ms_avg": {k: round(v, 5) for k, v in phase_avg.items()},
+        # the HBM-bound per-atom kernels: algorithmic bytes per atom x atoms / event-timed phase
+        "per_atom_kernels_hbm": {k: {"GBps": round(ALGO_BYTES_PER_ATOM[k] * N / (phase_avg[k] * 1e-3) / 1e9, 1),
+                                     "frac_of_8TBps": round(ALGO_BYTES_PER_ATOM[k] * N / (phase_avg[k] * 1e-3) / 8e12, 4),
+                                     "bytes_per_atom": ALGO_BYTES_PER_ATOM[k]} for k in ALGO_BYTES_PER_ATOM},
         "final_temperature_K": e_end["temperature"],
         "roofline": roofline,
         "cpu_baseline": cpu,
