@@ -218,7 +218,7 @@ def main():
             sn = MDSystem(ff, [melt.n_chains], melt.box[None, :], [wl.T0[0]], pos_prof, vel_prof, melt.types,
                           chain_len=wl.chain_len, dt=wl.dt_fs, tau=wl.tau_fs, precision="mixed", cell_div=0,
                           use_graph=not args.no_graph, device=dev, nl_skin=1.0, nl_every=10)
-            Rn, _ = sn.tuning()
+            Rn, sn_kern = sn.tuning()
             fn_lj = sn.forces(lj_only=True)
             sn.step(50)
             torch.cuda.synchronize(dev)
@@ -237,7 +237,14 @@ def main():
             nlist = {"value": N * n_nl / (b_ - a), "unit": "atom-steps/s", "steps": n_nl,
                      "ms_per_step": 1e3 * (b_ - a) / n_nl, "skin_A": 1.0, "rebuild_every": 10, "cell_div": Rn,
                      "phases_ms_avg": {k: round(v, 5) for k, v in ph.items()}, "status": status,
+                     "lj_kernel": sn_kern,
+                     # the list path's LJ force against the cell path's at the same positions,
+                     # over the RMS of the total force (reading of the 1e-5 criterion) and of the
+                     # LJ force alone
                      "lj_force_max_diff_vs_cell_path_over_frms": float(
+                         np.max(np.sqrt(np.sum((fn_lj - f_end_lj) ** 2, axis=0)))
+                         / np.sqrt(np.mean(np.sum(f_end ** 2, axis=0)))),
+                     "lj_force_max_diff_vs_cell_path_over_lj_frms": float(
                          np.max(np.sqrt(np.sum((fn_lj - f_end_lj) ** 2, axis=0)))
                          / np.sqrt(np.mean(np.sum(f_end_lj ** 2, axis=0))))}
             log("nlist: %.3f ms/step, %.3e atom-steps/s (%s)" % (nlist["ms_per_step"], nlist["value"], status))

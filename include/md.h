@@ -73,8 +73,11 @@ typedef enum {
                            atoms across the lanes */
   MD_LJ_CELLTILE_NB = 3, /* as MD_LJ_CELLTILE, with the pair force evaluated on every lane and
                             zeroed outside the cutoff instead of branching (mixed precision) */
-  MD_LJ_NLIST = 4        /* reported by md_tuning in neighbour-list mode (nl_skin > 0): one lane
-                            per atom walking its Verlet list; not a valid lj_kernel request */
+  MD_LJ_NLIST = 4,       /* neighbour-list mode (nl_skin > 0): a Verlet list per atom, one lane
+                            per atom walking it */
+  MD_LJ_NLIST_TILE = 5   /* neighbour-list mode: a list per cell (every atom within rc + skin of
+                            any atom of the cell at the build), streamed by the cell-tile kernel
+                            against the cell's atoms */
 } md_lj_kernel;
 
 typedef enum {
@@ -119,7 +122,8 @@ typedef struct {
   int32_t cell_div;           /* R: cells of edge >= rc / R, (2R+1)^3 cells visited;
                                  1 = the paper's grid (edge >= cutoff), 2 = half cells;
                                  0 = chosen by the autotuner at init */
-  int32_t lj_kernel;          /* md_lj_kernel (1..3, or 0 for the autotuner) */
+  int32_t lj_kernel;          /* md_lj_kernel: 1..3 (cell path) or 4..5 (neighbour-list mode), or 0
+                                 for the autotuner */
   int32_t use_graph;          /* 1: md_step replays a captured hipGraph of the step */
   double nl_skin;             /* > 0: neighbour-list mode.  A Verlet list of the pairs closer
                                  than rc + nl_skin (A) is built from the bins, and the bins and

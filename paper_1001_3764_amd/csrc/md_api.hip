@@ -88,7 +88,11 @@ md_status validate(const md_forcefield* ff, const md_config* cfg, std::string* w
   if (!finite_pos(cfg->dt_fs) || !finite_pos(cfg->tau_fs)) { *why = "dt and tau must be > 0"; return MD_ERR_ARG; }
   if (cfg->precision != MD_PREC_FP64 && cfg->precision != MD_PREC_MIXED) { *why = "bad precision"; return MD_ERR_ARG; }
   if (cfg->cell_div < 0 || cfg->cell_div > 3) { *why = "cell_div must be 0..3"; return MD_ERR_ARG; }
-  if (cfg->lj_kernel < 0 || cfg->lj_kernel > 3) { *why = "lj_kernel must be 0..3"; return MD_ERR_ARG; }
+  if (cfg->nl_skin > 0.0 ? !(cfg->lj_kernel == 0 || cfg->lj_kernel == MD_LJ_NLIST || cfg->lj_kernel == MD_LJ_NLIST_TILE)
+                         : (cfg->lj_kernel < 0 || cfg->lj_kernel > 3)) {
+    *why = "lj_kernel must be 0..3 (cell path) or 0, MD_LJ_NLIST, MD_LJ_NLIST_TILE (neighbour lists)";
+    return MD_ERR_ARG;
+  }
   if (cfg->integrator != MD_INT_VERLET_BERENDSEN && cfg->integrator != MD_INT_LEAPFROG_NH) {
     *why = "integrator must be MD_INT_VERLET_BERENDSEN or MD_INT_LEAPFROG_NH";
     return MD_ERR_ARG;
@@ -142,16 +146,29 @@ struct Plan {
   std::vector<BoxDev> boxes;
 };
 
-// List entries per atom: the pairs within rc + skin of the densest box, with room for
-// fluctuations (a list that fills up is reported as MD_ERR_NLIST).
-int32_t nl_capacity(const md_forcefield* ff, const md_config* cfg) {
-  double rho = 0.0;
-  for (int b = 0; b < cfg->n_boxes; ++b)
-    rho = std::max(rho, (double)cfg->n_chains[b] * cfg->chain_len /
-                            (cfg->box[3 * b] * cfg->box[3 * b + 1] * cfg->box[3 * b + 2]));
+// List capacity (a list that fills up is reported as MD_ERR_NLIST).  Per-atom lists: the
+// pairs within rc + skin at the densest box's density, 1.5x plus 64.  Per-cell lists: the
+// atoms that can lie within rc + skin of a cell, i.e. in the cell grown by rc + skin (a box
+// with rounded edges: V = e0 e1 e2 + 2 r (e0 e1 + e1 e2 + e2 e0) + pi r^2 (e0 + e1 + e2)
+// + 4/3 pi r^3), at the box's density, 1.25x plus 64, the largest over the boxes.
+int32_t nl_capacity(const md_forcefield* ff, const md_config* cfg, int R, int kernel) {
   const double rl = ff->rc + cfg->nl_skin;
-  const double mean = 4.0 / 3.0 * M_PI * rl * rl * rl * rho;
-  return (int32_t)((1.5 * mean + 64.0 + 15.0) / 16.0) * 16;
+  double need = 0.0;
+  for (int b = 0; b < cfg->n_boxes; ++b) {
+    const double* L = cfg->box + 3 * b;
+    const double rho = (double)cfg->n_chains[b] * cfg->chain_len / (L[0] * L[1] * L[2]);
+    if (kernel == MD_LJ_NLIST_TILE) {
+      double e[3];
+      for (int d = 0; d < 3; ++d) e[d] = L[d] / cells_per_dim(L[d], R, cell_reach(ff, cfg));
+      const double V = e[0] * e[1] * e[2] + 2.0 * rl * (e[0] * e[1] + e[1] * e[2] + e[2] * e[0]) +
+                       M_PI * rl * rl * (e[0] + e[1] + e[2]) + 4.0 / 3.0 * M_PI * rl * rl * rl;
+      need = std::max(need, 1.25 * V * rho + 64.0);
+    } else {
+      need = std::max(need, 1.5 * 4.0 / 3.0 * M_PI * rl * rl * rl * rho + 64.0);
+    }
+  }
+  const int q = kernel == MD_LJ_NLIST_TILE ? 64 : 16;
+  return (int32_t)((need + q - 1) / q) * q;
 }
 
 Plan make_plan(const md_forcefield* ff, const md_config* cfg, int R, int kernel) {
@@ -160,8 +177,8 @@ Plan make_plan(const md_forcefield* ff, const md_config* cfg, int R, int kernel)
   p.prec = cfg->precision;
   const bool nl = cfg->nl_skin > 0.0;
   if (nl) {
-    kernel = MD_LJ_NLIST;
-    p.nl_cap = nl_capacity(ff, cfg);
+    if (kernel != MD_LJ_NLIST_TILE) kernel = MD_LJ_NLIST;
+    p.nl_cap = nl_capacity(ff, cfg, R, kernel);
   }
   int64_t atom = 0, cell = 0, blk = 0, lblk = 0, cblk = 0, nle = 0;
   for (int b = 0; b < cfg->n_boxes; ++b) {
@@ -195,7 +212,7 @@ Plan make_plan(const md_forcefield* ff, const md_config* cfg, int R, int kernel)
     lblk += lj_blocks_for_box(kernel, n, nc);
     if (nl) {
       cblk += (nc + kTileWaves - 1) / kTileWaves;
-      nle += (n + 63) / 64 * 64 * (int64_t)p.nl_cap;
+      nle += (kernel == MD_LJ_NLIST_TILE ? nc : (n + 63) / 64 * 64) * (int64_t)p.nl_cap;
     }
     p.boxes.push_back(B);
   }
@@ -250,7 +267,7 @@ size_t carve(const Plan& p, char* base, Views* v) {
     t.n_cell_blocks = p.n_cell_blocks;
     t.cell_blk_box = (const int32_t*)take(4 * (size_t)p.n_cell_blocks);
     t.nl_list = (uint32_t*)take(4 * (size_t)p.nl_entries);
-    t.nl_count = (int32_t*)take(4 * (size_t)p.N);
+    t.nl_count = (int32_t*)take(4 * (size_t)std::max(p.N, p.C));
     t.x_build = (double*)take(24 * (size_t)p.N);
     t.slot_of = (int32_t*)take(4 * (size_t)p.N);
     t.pay_cur = take(psz * (size_t)p.N);
@@ -364,7 +381,7 @@ md_status configure(md_ctx* c, const md_config* cfg, int R, int kernel) {
   c->v = v;
   c->hboxes = p.boxes;
   c->R = R;
-  c->lj_kernel = p.nl_cap ? MD_LJ_NLIST : kernel;
+  c->lj_kernel = p.nl_cap && kernel != MD_LJ_NLIST_TILE ? MD_LJ_NLIST : kernel;
   c->since_build = 0;
   return MD_OK;
 }
@@ -378,7 +395,7 @@ void enqueue_rebuild(md_ctx* c, hipStream_t s, bool kick) {
   launch_scan(c->v, s);
   launch_scatter(c->v, s);
   launch_rank_payload(c->v, fp32, s);
-  if (nl_mode(c)) launch_nl_build(c->v, c->ffd, fp32, s);
+  if (nl_mode(c)) launch_nl_build(c->v, c->ffd, fp32, c->lj_kernel, s);
 }
 
 BondedMode bonded_mode(const md_ctx* c, bool step) {
@@ -391,7 +408,7 @@ BondedMode bonded_mode(const md_ctx* c, bool step) {
 void enqueue_forces(md_ctx* c, hipStream_t s, bool kick, bool energy, bool build_step = true) {
   const bool fp32 = c->prec == MD_PREC_MIXED;
   if (nl_mode(c))
-    launch_lj_nl(c->v, c->ffd, fp32, energy, build_step, s);
+    launch_lj_nl(c->v, c->ffd, fp32, c->lj_kernel, energy, build_step, s);
   else
     launch_lj(c->v, c->ffd, fp32, c->lj_kernel, energy, s);
   launch_bonded(c->v, c->ffd, fp32, bonded_mode(c, kick), energy, kick && c->remove_com, c->dt, s);
@@ -451,7 +468,12 @@ md_status autotune(md_ctx* c, const md_config* cfg, int* bestR, int* bestK) {
     for (int R = 1; R <= 2; ++R)
       if (grid_ok(&c->ff, cfg, R)) Rs.push_back(R);
   if (cfg->nl_skin > 0.0) {
-    Ks.push_back(MD_LJ_NLIST);
+    if (cfg->lj_kernel) {
+      Ks.push_back(cfg->lj_kernel);
+    } else {
+      Ks.push_back(MD_LJ_NLIST);
+      Ks.push_back(MD_LJ_NLIST_TILE);
+    }
     Rs.erase(std::remove_if(Rs.begin(), Rs.end(), [](int R) { return R > kTileMaxR; }), Rs.end());
   } else if (cfg->lj_kernel) Ks.push_back(cfg->lj_kernel);
   else {
@@ -470,14 +492,16 @@ md_status autotune(md_ctx* c, const md_config* cfg, int* bestR, int* bestK) {
   for (int R : Rs)
     for (int K : Ks) {
       if (Rs.size() * Ks.size() == 1) break;
-      if (K >= MD_LJ_CELLTILE && K != MD_LJ_NLIST && R > kTileMaxR) continue;
+      if (K >= MD_LJ_CELLTILE && R > kTileMaxR) continue;
       if ((st = configure(c, cfg, R, K))) break;
       enqueue_rebuild(c, c->stream, false);
       enqueue_forces(c, c->stream, false, false);
       (void)hipEventRecord(e0, c->stream);
       for (int rep = 0; rep < 3; ++rep) {
-        enqueue_rebuild(c, c->stream, false);
-        enqueue_forces(c, c->stream, false, false);
+        // neighbour lists: one build serves several force evaluations (all of them from the
+        // build's payload: nothing has refreshed the per-step payload here)
+        if (rep == 0 || !nl_mode(c)) enqueue_rebuild(c, c->stream, false);
+        enqueue_forces(c, c->stream, false, false, true);
       }
       (void)hipEventRecord(e1, c->stream);
       if ((st = hip_check(c, hipEventSynchronize(e1), "autotune sync"))) break;
@@ -509,10 +533,10 @@ md_status md_workspace_bytes(const md_forcefield* ff, const md_config* cfg, size
     if (cfg->cell_div && cfg->cell_div != R) continue;
     if (!cfg->cell_div && R > 2) continue;
     if (!grid_ok(ff, cfg, R)) continue;
-    for (int K = 1; K <= 3; ++K) {
+    for (int K = 1; K <= 5; ++K) {
       if (cfg->lj_kernel && cfg->lj_kernel != K) continue;
+      if ((cfg->nl_skin > 0.0) != (K >= MD_LJ_NLIST)) continue;
       if (K >= MD_LJ_CELLTILE && R > kTileMaxR) continue;
-      if (cfg->nl_skin > 0.0 && R > kTileMaxR) continue;
       best = std::max(best, carve(make_plan(ff, cfg, R, K), nullptr, nullptr));
       any = true;
     }
@@ -588,7 +612,7 @@ md_status md_init_system(const md_forcefield* ff, const md_config* cfg, double* 
   local.T0 = c->T0.data();
   int R = cfg->cell_div ? cfg->cell_div : 1;
   int K = cfg->lj_kernel ? cfg->lj_kernel : MD_LJ_ATOM;
-  if (!cfg->cell_div || (!cfg->lj_kernel && cfg->nl_skin <= 0.0)) st = autotune(c, &local, &R, &K);
+  if (!cfg->cell_div || !cfg->lj_kernel) st = autotune(c, &local, &R, &K);
   if (!st) st = configure(c, &local, R, K);
   if (!st) {
     enqueue_rebuild(c, c->stream, false);
@@ -681,11 +705,11 @@ md_status md_step_timed(md_ctx* c, int32_t n_steps, double* ms_out) {
     if (build) launch_rank_payload(c->v, fp32, s);
     (void)hipEventRecord(e[7], s);
     (void)hipEventRecord(e[14], s);
-    if (build && nl_mode(c)) launch_nl_build(c->v, c->ffd, fp32, s);
+    if (build && nl_mode(c)) launch_nl_build(c->v, c->ffd, fp32, c->lj_kernel, s);
     (void)hipEventRecord(e[15], s);
     (void)hipEventRecord(e[8], s);
     if (nl_mode(c))
-      launch_lj_nl(c->v, c->ffd, fp32, last, build, s);
+      launch_lj_nl(c->v, c->ffd, fp32, c->lj_kernel, last, build, s);
     else
       launch_lj(c->v, c->ffd, fp32, c->lj_kernel, last, s);
     (void)hipEventRecord(e[9], s);

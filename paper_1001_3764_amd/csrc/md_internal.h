@@ -106,13 +106,14 @@ struct Views {
   double* energy;      // [n_boxes * kEnergySlots] per-box results
   int32_t* err;        // sticky error word
   // neighbour-list mode (nl_cap = 0 otherwise)
-  int32_t nl_cap;              // list entries per atom
+  int32_t nl_cap;              // list entries per atom (per-atom lists) or per cell (per-cell lists)
   int32_t n_cell_blocks;       // list build blocks (kTileWaves home cells each)
   const int32_t* cell_blk_box; // [n_cell_blocks] box of each build block
-  uint32_t* nl_list;     // per box, per 64 atoms of sorted order: [nl_cap][64] entries
-                         // (sorted index << 7 | stencil code), entry t of atom s at
-                         // nl_off + (s/64) * 64 * nl_cap + t * 64 + s % 64 (s box-local)
-  int32_t* nl_count;     // [N] list length per sorted slot
+  uint32_t* nl_list;     // entries (sorted index << 7 | stencil code).  Per-atom lists: per
+                         // box, per 64 atoms of sorted order, [nl_cap][64]: entry t of atom s
+                         // at nl_off + (s/64) * 64 * nl_cap + t * 64 + s % 64 (s box-local).
+                         // Per-cell lists: entry t of box-local cell c at nl_off + c * nl_cap + t
+  int32_t* nl_count;     // list length per sorted slot [N] (per-atom lists) or per cell [C]
   double* x_build;       // [3N] wrapped positions at the last build (global order)
   int32_t* slot_of;      // [N] sorted slot of each atom at the last build
   void* pay_cur;         // [N] payload refreshed every step between builds
@@ -180,8 +181,10 @@ void launch_lj(const Views& v, const FFDev& ff, bool fp32, int kernel, bool ener
 int64_t lj_blocks_for_box(int kernel, int64_t n_atoms, int64_t n_cells);
 // neighbour-list mode: the list build (from the bins) and the LJ force from the list;
 // build_step: the payload of the build is current (else pay_cur is)
-void launch_nl_build(const Views& v, const FFDev& ff, bool fp32, hipStream_t s);
-void launch_lj_nl(const Views& v, const FFDev& ff, bool fp32, bool energy, bool build_step, hipStream_t s);
+// kernel: MD_LJ_NLIST (per-atom lists) or MD_LJ_NLIST_TILE (per-cell lists)
+void launch_nl_build(const Views& v, const FFDev& ff, bool fp32, int kernel, hipStream_t s);
+void launch_lj_nl(const Views& v, const FFDev& ff, bool fp32, int kernel, bool energy, bool build_step,
+                  hipStream_t s);
 constexpr int kLjNlBlock = 256;   // threads per block of the list force kernel (box-aligned)
 constexpr int kTileWaves = 4;     // home cells per block of the cell-tile kernel
 constexpr int kXcds = 8;          // accelerator complex dies of an MI355X (one L2 each)

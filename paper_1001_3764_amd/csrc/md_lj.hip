@@ -354,6 +354,23 @@ __device__ __forceinline__ int fill_list(const Views& v, const BoxDev& B, int lc
   return total;
 }
 
+// The candidate list of home cell lc, entries [c0, c0 + kListCap), into list[]; returns its
+// full length.  Cell path: the whole stencil, listed here.  Neighbour-list mode with cell
+// lists (LIST): the cell's own list, the candidates within rc + skin of any of its atoms at
+// the last build (k_nl_build_tile), copied from HBM.
+template <bool LIST>
+__device__ __forceinline__ int load_list(const Views& v, const BoxDev& B, int lc, int c0, uint32_t* list) {
+  if constexpr (!LIST) {
+    return fill_list(v, B, lc, c0, list);
+  } else {
+    const int n = v.nl_count[B.cell_off + lc];
+    const uint32_t* __restrict__ src = v.nl_list + B.nl_off + (int64_t)lc * v.nl_cap;
+    const int m = min(kListCap, n - c0);
+    for (int t = lane(); t < m; t += 64) list[t] = src[c0 + t];
+    return n;
+  }
+}
+
 struct BandEnergy {
   double e, es, w;
 };
@@ -367,7 +384,7 @@ struct BandEnergy {
 // expected in a melt) every candidate of the group is walked again instead.  LDS executes
 // a wave's accesses in order and only this wave wrote its slots, so no barrier is needed.
 // `resident` is the chunk the list holds; it is updated.
-template <bool ENERGY, bool UNI>
+template <bool ENERGY, bool UNI, bool LIST>
 __device__ __forceinline__ BandEnergy settle_band_group(const Views& v, int chain_len, int excl, double rc2,
                                                         const LjPair<float>& cf, const BoxDev& B, Band bd, int lc,
                                                         int total, uint32_t* list, int& resident,
@@ -402,7 +419,7 @@ __device__ __forceinline__ BandEnergy settle_band_group(const Views& v, int chai
       const int fs = steps[s];
       const int c0 = fs - fs % kListCap;
       if (c0 != resident) {
-        fill_list(v, B, lc, c0, list);
+        load_list<LIST>(v, B, lc, c0, list);
         resident = c0;
       }
       int jx, jy, jz;
@@ -461,7 +478,7 @@ __device__ __forceinline__ BandEnergy settle_band_group(const Views& v, int chai
       float bx = 0.0f, by = 0.0f, bz = 0.0f;
       for (int c0 = 0; c0 < total; c0 += kListCap) {
         if (c0 != resident) {
-          fill_list(v, B, lc, c0, list);
+          load_list<LIST>(v, B, lc, c0, list);
           resident = c0;
         }
         const int cn = min(kListCap, total - c0);
@@ -498,7 +515,9 @@ __device__ __forceinline__ BandEnergy settle_band_group(const Views& v, int chai
 // Occupancy targets (measured): the mixed form is held to 6 waves per SIMD (80 VGPRs; left
 // alone the compiler takes 82 and runs 5, and the few values it then spills sit outside the
 // pair loop: 8% faster); the FP64 form (K = 4) fits 8.
-template <bool FP64, bool ENERGY, bool UNI, int KMAX, bool BRANCHLESS>
+// LIST: neighbour-list mode with per-cell lists (the homes and the sorted order are those of
+// the last build, the payload the one refreshed since).
+template <bool FP64, bool ENERGY, bool UNI, int KMAX, bool BRANCHLESS, bool LIST = false>
 __global__ __launch_bounds__(64 * kTileWaves) __attribute__((amdgpu_waves_per_eu(FP64 ? 8 : 6)))
 void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
   using PayT = std::conditional_t<FP64, Pay64, int4>;
@@ -537,7 +556,7 @@ void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
     }
   }
   int total = 0, resident = 0;
-  if (wact) total = __builtin_amdgcn_readfirstlane(fill_list(v, B, lc, 0, list[wave]));
+  if (wact) total = __builtin_amdgcn_readfirstlane(load_list<LIST>(v, B, lc, 0, list[wave]));
   __syncthreads();
 
   double e = 0.0, es = 0.0, w = 0.0;
@@ -587,7 +606,7 @@ void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
       int32_t bmax = 0;     // bits of the largest r2s counted since the last band check
       for (int c0 = 0; c0 < total; c0 += kListCap) {
         if (c0 != resident) {
-          fill_list(v, B, lc, c0, list[wave]);
+          load_list<LIST>(v, B, lc, c0, list[wave]);
           resident = c0;
         }
         const int cn = min(kListCap, total - c0);
@@ -658,7 +677,7 @@ void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
       }
       if constexpr (!FP64) {
         if (nsteps > 0) {
-          const BandEnergy be = settle_band_group<ENERGY, UNI>(v, ff.chain_len, ff.excl, ff.rc2, cf, B, bd, lc,
+          const BandEnergy be = settle_band_group<ENERGY, UNI, LIST>(v, ff.chain_len, ff.excl, ff.rc2, cf, B, bd, lc,
                                                                total, list[wave], resident, shifts, bsteps[wave],
                                                                bq[wave], pay, hs, g0, kc, nsteps);
           if (ENERGY) {
@@ -795,6 +814,91 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_nl_build(Views v, FFDev ff)
   }
 }
 
+// Build with per-cell lists: one wave per home cell streams its stencil as the cell tile
+// does and keeps every candidate within rc + skin of ANY atom of the cell (the union of
+// their Verlet spheres, in stencil order), so the force kernel can stream it exactly like
+// the stencil (k_lj_tile<LIST>): fewer candidates, the same coalesced loads.  Home atoms
+// and excluded partners stay in the list (the force kernel tests exclusions per pair).
+template <bool FP64>
+__global__ __launch_bounds__(64 * kTileWaves) void k_nl_build_tile(Views v, FFDev ff) {
+  using PayT = std::conditional_t<FP64, Pay64, int4>;
+  using Q = std::conditional_t<FP64, double, int>;
+  __shared__ uint32_t list[kTileWaves][kListCap];
+  __shared__ Shift<Q> shifts[kMaxStencil];
+
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const int ln = lane();
+  const int per_xcd = (int)gridDim.x / kXcds;
+  const int blk = ((int)blockIdx.x % kXcds) * per_xcd + (int)blockIdx.x / kXcds;
+  if (blk >= v.n_cell_blocks) return;
+  const BoxDev& B = v.boxes[v.cell_blk_box[blk]];
+  const int lc = (blk - B.cell_blk_off) * kTileWaves + wave;
+  const bool wact = lc < B.n_cells;
+  const PayT* __restrict__ pay = static_cast<const PayT*>(v.payload);
+  {
+    const int R = v.R, W = 2 * R + 1;
+    const int code = (int)threadIdx.x;
+    if (code < W * W * W) {
+      const int ox = code % W - R, oy = (code / W) % W - R, oz = code / (W * W) - R;
+      if constexpr (FP64)
+        shifts[code] = Shift<Q>{ox * B.edge[0], oy * B.edge[1], oz * B.edge[2]};
+      else
+        shifts[code] = Shift<Q>{ox * B.edge_q[0], oy * B.edge_q[1], oz * B.edge_q[2]};
+    }
+  }
+  int total = 0, resident = 0;
+  if (wact) total = __builtin_amdgcn_readfirstlane(fill_list(v, B, lc, 0, list[wave]));
+  __syncthreads();
+  if (!wact) return;
+  const int hs = __builtin_amdgcn_readfirstlane(v.cell_start[B.cell_off + lc]);
+  const int hn = __builtin_amdgcn_readfirstlane(v.cell_start[B.cell_off + lc + 1]) - hs;
+  // list radius, widened a little: the list may hold extra pairs, never miss one
+  const double rl2 = v.nl_rl2 * (1.0 + 1e-5);
+  const float rl2s = (float)(rl2 * kFix * kFix);
+  const int cap = v.nl_cap;
+  uint32_t* __restrict__ out = v.nl_list + B.nl_off + (int64_t)lc * cap;
+  int cnt = 0;
+  for (int c0 = 0; c0 < total; c0 += kListCap) {
+    if (c0 != resident) {
+      fill_list(v, B, lc, c0, list[wave]);
+      resident = c0;
+    }
+    const int cn = min(kListCap, total - c0);
+    for (int t0 = 0; t0 < cn; t0 += 64) {
+      const bool act = t0 + ln < cn;
+      uint32_t ent = 0;
+      Q jx = (Q)0, jy = (Q)0, jz = (Q)0;
+      if (act) {
+        ent = list[wave][t0 + ln];
+        const PayT q = pay[ent >> 7];
+        const Shift<Q> sh = shifts[ent & 127];
+        jx = q.x + sh.x;
+        jy = q.y + sh.y;
+        jz = q.z + sh.z;
+      }
+      bool hit = false;
+      for (int h = 0; h < hn; ++h) {
+        const PayT q = pay[hs + h];
+        if constexpr (FP64) {
+          const double dx = q.x - jx, dy = q.y - jy, dz = q.z - jz;
+          hit = hit || dx * dx + dy * dy + dz * dz < rl2;
+        } else {
+          hit = hit || r2_fix((float)(q.x - jx), (float)(q.y - jy), (float)(q.z - jz)) < rl2s;
+        }
+      }
+      hit = hit && act;
+      const uint64_t m = __ballot(hit);
+      const int at = cnt + lanes_below(m);
+      if (hit && at < cap) out[at] = ent;
+      cnt += __popcll(m);
+    }
+  }
+  if (ln == 0) {
+    v.nl_count[B.cell_off + lc] = min(cnt, cap);
+    if (cnt > cap) atomicOr(v.err, (int)kErrNlFull);
+  }
+}
+
 // LJ force from the lists: one lane per atom of sorted order, walking its list; the
 // candidate comes from the current payload plus the stencil shift recorded at the
 // build.  Mixed form: FP32 on exact int32 differences, with the cutoff band decided in
@@ -910,41 +1014,61 @@ LjPair<P> make_pair(const FFDev& ff) {
   return c;
 }
 
-template <bool FP64, bool ENERGY>
+template <bool FP64, bool ENERGY, bool LIST = false>
 void launch_tile(const Views& v, const FFDev& ff, const LjPair<float>& cf, const LjPair<double>& cd,
                  bool branchless, hipStream_t s) {
   dim3 g((v.n_lj_blocks + kXcds - 1) / kXcds * kXcds), b(64 * kTileWaves);
   constexpr int K = FP64 ? 4 : kTileHomesMixed;
   if (ff.uniform_lj) {
-    if (branchless)
+    if (branchless && !LIST)
       hipLaunchKernelGGL((k_lj_tile<FP64, ENERGY, true, K, true>), g, b, 0, s, v, ff, cf, cd);
     else
-      hipLaunchKernelGGL((k_lj_tile<FP64, ENERGY, true, K, false>), g, b, 0, s, v, ff, cf, cd);
+      hipLaunchKernelGGL((k_lj_tile<FP64, ENERGY, true, K, false, LIST>), g, b, 0, s, v, ff, cf, cd);
   } else {
-    hipLaunchKernelGGL((k_lj_tile<FP64, ENERGY, false, K, false>), g, b, 0, s, v, ff, cf, cd);
+    hipLaunchKernelGGL((k_lj_tile<FP64, ENERGY, false, K, false, LIST>), g, b, 0, s, v, ff, cf, cd);
   }
 }
 
 }  // namespace
 
 int64_t lj_blocks_for_box(int kernel, int64_t n_atoms, int64_t n_cells) {
-  if (kernel == 2 || kernel == 3) return (n_cells + kTileWaves - 1) / kTileWaves;
+  if (kernel == 2 || kernel == 3 || kernel == 5) return (n_cells + kTileWaves - 1) / kTileWaves;
   if (kernel == 4) return (n_atoms + kLjNlBlock - 1) / kLjNlBlock;
   return (n_atoms + kLjAtomBlock - 1) / kLjAtomBlock;
 }
 
-void launch_nl_build(const Views& v, const FFDev& ff, bool fp32, hipStream_t s) {
+void launch_nl_build(const Views& v, const FFDev& ff, bool fp32, int kernel, hipStream_t s) {
   dim3 g((v.n_cell_blocks + kXcds - 1) / kXcds * kXcds), b(64 * kTileWaves);
+  if (kernel == 5) {
+    if (fp32)
+      hipLaunchKernelGGL((k_nl_build_tile<false>), g, b, 0, s, v, ff);
+    else
+      hipLaunchKernelGGL((k_nl_build_tile<true>), g, b, 0, s, v, ff);
+    return;
+  }
   if (fp32)
     hipLaunchKernelGGL((k_nl_build<false, kTileHomesMixed>), g, b, 0, s, v, ff);
   else
     hipLaunchKernelGGL((k_nl_build<true, 4>), g, b, 0, s, v, ff);
 }
 
-void launch_lj_nl(const Views& v, const FFDev& ff, bool fp32, bool energy, bool build_step, hipStream_t s) {
+void launch_lj_nl(const Views& v, const FFDev& ff, bool fp32, int kernel, bool energy, bool build_step,
+                  hipStream_t s) {
   const LjPair<float> cf = make_pair<float>(ff);
   const LjPair<double> cd = make_pair<double>(ff);
   const void* pay = build_step ? v.payload : v.pay_cur;
+  if (kernel == 5) {   // per-cell lists through the cell tile, reading the current payload
+    Views w = v;
+    w.payload = const_cast<void*>(pay);
+    if (fp32) {
+      if (energy) launch_tile<false, true, true>(w, ff, cf, cd, false, s);
+      else launch_tile<false, false, true>(w, ff, cf, cd, false, s);
+    } else {
+      if (energy) launch_tile<true, true, true>(w, ff, cf, cd, false, s);
+      else launch_tile<true, false, true>(w, ff, cf, cd, false, s);
+    }
+    return;
+  }
   dim3 g(v.n_lj_blocks), b(kLjNlBlock);
 #define MDK_NL(F64, E, U) hipLaunchKernelGGL((k_lj_nl<F64, E, U>), g, b, 0, s, v, ff, cf, cd, pay)
   if (fp32) {

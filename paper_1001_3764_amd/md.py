@@ -19,7 +19,7 @@ LIB_PATH = os.environ.get("PAPER_1001_3764_AMD_LIB") or os.path.join(
 MD_OK, MD_ERR_ARG, MD_ERR_BOX_TOO_SMALL, MD_ERR_NONFINITE = 0, -1, -2, -3
 MD_ERR_WORKSPACE, MD_ERR_HIP, MD_ERR_STATE, MD_ERR_NLIST = -4, -6, -7, -8
 MD_PREC_FP64, MD_PREC_MIXED = 0, 1
-MD_LJ_AUTO, MD_LJ_ATOM, MD_LJ_CELLTILE, MD_LJ_CELLTILE_NB, MD_LJ_NLIST = 0, 1, 2, 3, 4
+MD_LJ_AUTO, MD_LJ_ATOM, MD_LJ_CELLTILE, MD_LJ_CELLTILE_NB, MD_LJ_NLIST, MD_LJ_NLIST_TILE = 0, 1, 2, 3, 4, 5
 MD_INT_VERLET_BERENDSEN, MD_INT_LEAPFROG_NH = 0, 1
 
 _D, _I32, _I64, _P = ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
@@ -245,9 +245,11 @@ class MDSystem:
     library owns every computation on them."""
 
     def __init__(self, ff: dict, n_chains, boxes, T0, pos, vel, types, chain_len=300, dt=1.0, tau=100.0,
-                 precision="mixed", cell_div=1, lj_kernel=MD_LJ_ATOM, use_graph=False, device="cuda:0",
+                 precision="mixed", cell_div=1, lj_kernel=None, use_graph=False, device="cuda:0",
                  nl_skin=0.0, nl_every=10, integrator="verlet", remove_com=False):
-        """nl_skin > 0: neighbour-list mode (bins and list rebuilt every nl_every steps).
+        """lj_kernel: an md_lj_kernel; None is MD_LJ_ATOM on the cell path and the autotuner
+        (0) in neighbour-list mode.
+        nl_skin > 0: neighbour-list mode (bins and list rebuilt every nl_every steps).
         integrator: "verlet" (velocity Verlet, Berendsen when T0 > 0) or "leapfrog" (leap-frog,
         Nose-Hoover when T0 > 0, tau the thermostat period; vel holds half-step velocities).
         remove_com: subtract each box's centre-of-mass velocity after every step."""
@@ -255,6 +257,8 @@ class MDSystem:
         self.device = torch.device(device)
         self.ff = make_forcefield(ff)
         integ = {"verlet": MD_INT_VERLET_BERENDSEN, "leapfrog": MD_INT_LEAPFROG_NH}.get(integrator, integrator)
+        if lj_kernel is None:
+            lj_kernel = MD_LJ_AUTO if nl_skin > 0 else MD_LJ_ATOM
         self.cfg = _Config(n_chains, boxes, T0, chain_len, dt, tau, precision, cell_div, lj_kernel, use_graph,
                            nl_skin, nl_every, integ, remove_com)
         self.n_boxes = self.cfg.c.n_boxes

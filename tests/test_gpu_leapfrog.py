@@ -112,7 +112,7 @@ def test_leapfrog_batched_boxes(ff):
 def test_leapfrog_graph_and_timed_steps_are_bit_identical(ff, melt, nl):
     kw = dict(cell_div=2, T0=330.0, vel=melt.vel + W, integrator="leapfrog", remove_com=True)
     if nl:
-        kw.update(nl_skin=1.0, nl_every=4)
+        kw.update(nl_skin=1.0, nl_every=4, lj_kernel=5)
     else:
         kw.update(lj_kernel=2)
     a = system(ff, melt, "mixed", use_graph=False, **kw)
@@ -134,8 +134,8 @@ def test_leapfrog_graph_and_timed_steps_are_bit_identical(ff, melt, nl):
 
 def test_leapfrog_neighbour_list_against_oracle(ff, melt):
     T0 = 350.0
-    s = system(ff, melt, "mixed", T0, vel=melt.vel + W, cell_div=2, nl_skin=1.0, nl_every=5, use_graph=True,
-               integrator="leapfrog", remove_com=True)
+    s = system(ff, melt, "mixed", T0, vel=melt.vel + W, cell_div=2, nl_skin=1.0, nl_every=5, lj_kernel=5,
+               use_graph=True, integrator="leapfrog", remove_com=True)
     f0, _ = O.forces(ff, melt.pos, melt.types, melt.box, 300)
     s.step(40)
     po, _, _, eo = O.run_leapfrog(ff, melt.pos, melt.vel + W, f0, melt.types, melt.box, 300, 40, T0=T0,

@@ -22,21 +22,25 @@ def melt():
     return make_melt(10, density=0.80, T=500.0, seed_melt=1000, seed_vel=1001, jitter=0.05)
 
 
-def system(m, ff, precision, R=1, T0=0.0, skin=SKIN, every=10, **kw):
+KERNELS = [4, 5]   # MD_LJ_NLIST (a list per atom), MD_LJ_NLIST_TILE (a list per cell)
+
+
+def system(m, ff, precision, R=1, T0=0.0, skin=SKIN, every=10, kernel=4, **kw):
     from paper_1001_3764_amd.md import MDSystem
-    print("nlist system: N=%d %s R=%d skin=%g every=%d %s" % (m.n_atoms, precision, R, skin, every, kw), flush=True)
+    print("nlist system: N=%d %s R=%d kernel=%d skin=%g every=%d %s" % (m.n_atoms, precision, R, kernel, skin,
+                                                                      every, kw), flush=True)
     return MDSystem(ff, [m.n_chains], m.box[None, :], [T0], m.pos, m.vel, m.types, chain_len=m.chain_len,
-                    precision=precision, cell_div=R, nl_skin=skin, nl_every=every, **kw)
+                    precision=precision, cell_div=R, nl_skin=skin, nl_every=every, lj_kernel=kernel, **kw)
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("R", [1, 2])
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
-def test_nlist_bins_forces_energies(ff, melt, precision, R):
+def test_nlist_bins_forces_energies(ff, melt, precision, R, kernel):
     """Bins are bit-exact on the grid of edge >= (rc + skin) / R; forces and energies from
     the list equal the oracle's."""
-    from paper_1001_3764_amd.md import MD_LJ_NLIST
-    s = system(melt, ff, precision, R)
-    assert s.tuning() == (R, MD_LJ_NLIST)
+    s = system(melt, ff, precision, R, kernel=kernel)
+    assert s.tuning() == (R, kernel)
     M, _, _ = s.grid(0)
     assert np.all(M == np.floor(melt.box * R / (ff["rc"] + SKIN)))
     start, atoms = s.bins()
@@ -58,11 +62,12 @@ def test_nlist_bins_forces_energies(ff, melt, precision, R):
     s.close()
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("precision,xtol", [("fp64", 1e-9), ("mixed", 1e-4)])
-def test_nlist_trajectory_100_steps(ff, melt, precision, xtol):
+def test_nlist_trajectory_100_steps(ff, melt, precision, xtol, kernel):
     """100 NVE steps with the list rebuilt every 10: positions against the oracle (which
     searches the cells every step), checked every 25 steps, between builds too."""
-    s = system(melt, ff, precision, 2)
+    s = system(melt, ff, precision, 2, kernel=kernel)
     f0, _ = O.forces(ff, melt.pos, melt.types, melt.box, 300)
     p_o, v_o, f_o = melt.pos, melt.vel, f0
     worst = []
@@ -82,14 +87,15 @@ def test_nlist_trajectory_100_steps(ff, melt, precision, xtol):
     s.close()
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
-def test_nlist_matches_cell_path(ff, melt, precision):
+def test_nlist_matches_cell_path(ff, melt, precision, kernel):
     """The same 30 Berendsen steps through the cell path and the list path (rebuilt every
     7): the same pairs, so the same trajectory up to summation order."""
     from paper_1001_3764_amd.md import MDSystem
     a = MDSystem(ff, [melt.n_chains], melt.box[None, :], [350.0], melt.pos, melt.vel, melt.types,
                  precision=precision, cell_div=2, lj_kernel=2)
-    b = system(melt, ff, precision, 2, T0=350.0, every=7)
+    b = system(melt, ff, precision, 2, T0=350.0, every=7, kernel=kernel)
     a.step(30)
     b.step(30)
     pa, va = a.state()
@@ -104,10 +110,11 @@ def test_nlist_matches_cell_path(ff, melt, precision):
     b.close()
 
 
-def test_nlist_graph_replay_and_timed_steps_are_bit_identical(ff, melt):
-    a = system(melt, ff, "mixed", 2, T0=400.0, use_graph=False, every=4)
-    b = system(melt, ff, "mixed", 2, T0=400.0, use_graph=True, every=4)
-    c = system(melt, ff, "mixed", 2, T0=400.0, use_graph=False, every=4)
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_nlist_graph_replay_and_timed_steps_are_bit_identical(ff, melt, kernel):
+    a = system(melt, ff, "mixed", 2, T0=400.0, use_graph=False, every=4, kernel=kernel)
+    b = system(melt, ff, "mixed", 2, T0=400.0, use_graph=True, every=4, kernel=kernel)
+    c = system(melt, ff, "mixed", 2, T0=400.0, use_graph=False, every=4, kernel=kernel)
     for n in (3, 7, 6):
         a.step(n)
         b.step(n)
@@ -123,7 +130,8 @@ def test_nlist_graph_replay_and_timed_steps_are_bit_identical(ff, melt):
         s.close()
 
 
-def test_nlist_batched_boxes(ff):
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_nlist_batched_boxes(ff, kernel):
     """Three boxes of different sizes in one list-mode context: each box against the
     oracle after 20 steps (lists rebuilt every 6)."""
     from paper_1001_3764_amd.md import MDSystem
@@ -134,7 +142,7 @@ def test_nlist_batched_boxes(ff):
     types = np.concatenate([m.types for m in melts])
     T0 = [280.0, 0.0, 420.0]
     s = MDSystem(ff, [m.n_chains for m in melts], np.stack([m.box for m in melts]), T0, pos, vel, types,
-                 precision="mixed", cell_div=2, nl_skin=SKIN, nl_every=6)
+                 precision="mixed", cell_div=2, nl_skin=SKIN, nl_every=6, lj_kernel=kernel)
     f_all = s.forces()
     s.step(20)
     p_all, _ = s.state()
@@ -152,11 +160,12 @@ def test_nlist_batched_boxes(ff):
     s.close()
 
 
-def test_nlist_skin_exceeded_is_reported(ff, melt):
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_nlist_skin_exceeded_is_reported(ff, melt, kernel):
     """A skin far too thin for the list's lifetime: the step reports MD_ERR_NLIST (the
     device flags the displacement; nothing faults) and the context refuses further steps."""
     from paper_1001_3764_amd.md import MD_ERR_NLIST, MD_ERR_STATE, MDError
-    s = system(melt, ff, "mixed", 2, skin=0.02, every=100)
+    s = system(melt, ff, "mixed", 2, skin=0.02, every=100, kernel=kernel)
     s.step(60)
     with pytest.raises(MDError) as ex:
         s.energies()
@@ -167,8 +176,9 @@ def test_nlist_skin_exceeded_is_reported(ff, melt):
     s.close()
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
-def test_nlist_pairs_at_the_cutoff(ff, precision):
+def test_nlist_pairs_at_the_cutoff(ff, precision, kernel):
     """Facing pairs at rc (1 + delta), delta in [-4e-7, 4e-7]: the list path counts exactly
     the FP64 pair set too."""
     rc = ff["rc"]
@@ -184,9 +194,21 @@ def test_nlist_pairs_at_the_cutoff(ff, precision):
     fo, _ = O.lj_brute(ff, pos, types, box, n)
     from paper_1001_3764_amd.md import MDSystem
     s = MDSystem(ff, [2], box[None, :], [0.0], pos, np.zeros_like(pos), types, chain_len=n,
-                 precision=precision, cell_div=2, nl_skin=SKIN, nl_every=5)
+                 precision=precision, cell_div=2, nl_skin=SKIN, nl_every=5, lj_kernel=kernel)
     flj = s.forces(lj_only=True)
     s.close()
     s6 = ff["sigma"][0] ** 6
     f_rc = 4 * ff["epsilon"][0] * (12 * s6 * s6 / rc ** 13 - 6 * s6 / rc ** 7)
     assert np.max(np.abs(flj - fo)) < 0.02 * abs(f_rc)
+
+
+def test_nlist_autotuner_picks_a_list_kernel(ff, melt):
+    """lj_kernel = 0 in list mode: the autotuner times both list layouts and the result
+    still equals the oracle."""
+    s = system(melt, ff, "mixed", 0, kernel=0)
+    R, kern = s.tuning()
+    print("list mode tuned to R=%d kernel=%d" % (R, kern), flush=True)
+    assert R in (1, 2) and kern in KERNELS
+    fo, _ = O.lj_cells(ff, melt.pos, melt.types, melt.box, 300)
+    assert norm_err(s.forces(lj_only=True), fo) <= TOL["mixed"]
+    s.close()

@@ -72,7 +72,7 @@ def test_observables_of_the_initial_melt(ff, melt, R):
 def test_observables_after_steps(ff, melt, nl):
     """After 23 steps (between list builds in neighbour-list mode: the cell lists are those
     of the last build, the positions current)."""
-    kw = dict(nl_skin=1.0, nl_every=10) if nl else dict(lj_kernel=2)
+    kw = dict(nl_skin=1.0, nl_every=10, lj_kernel=5) if nl else dict(lj_kernel=2)
     s = system(ff, [melt], precision="mixed", cell_div=2, use_graph=True, **kw)
     s.step(23)
     pos, _ = s.state()

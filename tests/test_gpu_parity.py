@@ -209,7 +209,8 @@ def test_pairs_at_the_cutoff(ff, precision, R, kernel):
 
 
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
-@pytest.mark.parametrize("R,kernel,nl", [(1, 2, False), (2, 2, False), (2, 3, False), (2, 1, False), (1, 0, True)])
+@pytest.mark.parametrize("R,kernel,nl", [(1, 2, False), (2, 2, False), (2, 3, False), (2, 1, False), (1, 4, True),
+                                         (1, 5, True), (2, 5, True)])
 def test_many_pairs_at_the_cutoff(ff, precision, R, kernel, nl):
     """One atom with 100 partners on a sphere of radius rc (1 + delta), |delta| <= 4e-7: more
     band pairs than the cell tile's queue holds (64), spread over more than its 8 recorded
@@ -235,10 +236,10 @@ def test_many_pairs_at_the_cutoff(ff, precision, R, kernel, nl):
     assert np.array_equal(np.sum(d * d, axis=0) < rc * rc, delta < 0)   # the oracle's own pair set
     from paper_1001_3764_amd.md import MDSystem
     print("many cutoff pairs: precision=%s R=%d kernel=%d nl=%s" % (precision, R, kernel, nl), flush=True)
-    kw = dict(nl_skin=1.0, nl_every=5) if nl else dict(lj_kernel=kernel)
+    kw = dict(nl_skin=1.0, nl_every=5, lj_kernel=kernel) if nl else dict(lj_kernel=kernel)
     s = MDSystem(ff, [pos.shape[1] // 4], box[None, :], [0.0], pos, np.zeros_like(pos), types, chain_len=4,
                  precision=precision, cell_div=R, **kw)
-    if nl:
+    if nl and kernel == 4:
         # the list holds 1.5x the mean neighbour count of this sparse box plus 79 (80 entries):
         # the centre's 100 partners overflow it, which is reported, not silently truncated
         from paper_1001_3764_amd.md import MD_ERR_NLIST, MDError
