@@ -2,6 +2,7 @@
 benchmark times: mixed precision, autotuned stencil radius and LJ kernel, graph-replayed
 steps.  The oracle computes sampled atoms one by one where the whole system would take too
 long, and the whole system where it is cheap (bins, bonded terms, the smallest box)."""
+import dataclasses
 import os
 
 import numpy as np
@@ -142,6 +143,21 @@ def test_melt300k_leapfrog_nose_hoover_50_steps(ff, melt300k):
     assert e["temperature"] == pytest.approx(eo["temperature"], rel=1e-5)
     assert e["nh_xi"] == pytest.approx(eo["xi"], rel=1e-4)
     assert e["e_thermostat"] == pytest.approx(eo["e_thermostat"], rel=1e-4)
+
+
+def test_melt300k_neighbour_lists_sampled_forces(ff, melt300k):
+    """The list form as the benchmark runs it (skin 1 A, rebuilt every 10 steps, autotuned
+    layout): 15 steps in, so the forces come from the refreshed payload between builds; every
+    bonded force and 2,000 sampled LJ forces against the oracle at the current positions."""
+    wl = WORKLOADS["melt300k_mixed"]
+    s = system(ff, [melt300k], wl, cell_div=0, use_graph=True, nl_skin=1.0, nl_every=10)
+    print("tuned (R, kernel) =", s.tuning(), flush=True)
+    s.step(15)
+    pos, _ = s.state()
+    s.compute_forces(True)
+    cur = dataclasses.replace(melt300k, pos=pos)
+    check_sampled_forces(ff, s, cur, 2000, 31)
+    s.close()
 
 
 def test_melt3M_bins_and_sampled_forces(ff):
