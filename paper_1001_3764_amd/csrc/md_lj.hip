@@ -651,28 +651,52 @@ void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
           }
         }
       }
-      // sum each home atom's partial forces over the 64 lanes (fixed butterfly order)
+      // Sum each home atom's partial forces over the 64 lanes in a fixed order.  Recursive
+      // halving: at each of the first log2(KMAX) levels a lane keeps half of its values and
+      // adds the partner's copy of that half, so the 3 KMAX sums take 3 KMAX - 3 exchanges
+      // (instead of 18 KMAX for separate butterflies); then a butterfly over the remaining
+      // lanes, after which lanes [h * 64/KMAX, (h + 1) * 64/KMAX) hold home h's sums, and lane
+      // k fetches home k's (the lane that stores a home also applies its band corrections).
       P* f = static_cast<P*>(v.f_lj);
+      {
+        constexpr int LV = KMAX == 8 ? 3 : (KMAX == 4 ? 2 : (KMAX == 2 ? 1 : 0));
+        static_assert((1 << LV) == KMAX, "KMAX must be 1, 2, 4 or 8");
+        constexpr int NV = 3 * KMAX;
+        P val[NV];
 #pragma unroll
-      for (int k = 0; k < KMAX; ++k) {
-        if (k < kc) {
-          P sx = ax[k], sy = ay[k], sz = az[k];
-          for (int off = 32; off > 0; off >>= 1) {
-            sx += __shfl_xor(sx, off);
-            sy += __shfl_xor(sy, off);
-            sz += __shfl_xor(sz, off);
+        for (int k = 0; k < KMAX; ++k) {
+          val[3 * k] = ax[k];
+          val[3 * k + 1] = ay[k];
+          val[3 * k + 2] = az[k];
+        }
+#pragma unroll
+        for (int lv = 0; lv < LV; ++lv) {
+          const int off = 32 >> lv;
+          const bool hi = (ln & off) != 0;
+#pragma unroll
+          for (int i = 0; i < (NV >> lv) / 2; ++i) {
+            const int h = (NV >> lv) / 2 + i;
+            const P send = hi ? val[i] : val[h];
+            const P keep = hi ? val[h] : val[i];
+            val[i] = keep + __shfl_xor(send, off);
           }
-          if constexpr (!FP64) {
-            sx *= fscale;
-            sy *= fscale;
-            sz *= fscale;
-          }
-          if (ln == k) {
-            const int32_t i = tag_index(pay_tag(pay[hs + g0 + k]));
-            f[i] = sx;
-            f[v.N + i] = sy;
-            f[2 * v.N + i] = sz;
-          }
+        }
+#pragma unroll
+        for (int lv = LV; lv < 6; ++lv)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) val[c] += __shfl_xor(val[c], 32 >> lv);
+        const int src = (ln & (KMAX - 1)) << (6 - LV);
+        P sx = __shfl(val[0], src), sy = __shfl(val[1], src), sz = __shfl(val[2], src);
+        if constexpr (!FP64) {
+          sx *= fscale;
+          sy *= fscale;
+          sz *= fscale;
+        }
+        if (ln < kc) {
+          const int32_t i = tag_index(pay_tag(pay[hs + g0 + ln]));
+          f[i] = sx;
+          f[v.N + i] = sy;
+          f[2 * v.N + i] = sz;
         }
       }
       if constexpr (!FP64) {
