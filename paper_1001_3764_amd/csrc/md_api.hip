@@ -312,6 +312,10 @@ FFDev make_ffdev(const md_forcefield* ff, int chain_len) {
   d.n_dih = ff->n_dih;
   d.excl = ff->excl_depth;
   d.chain_len = chain_len;
+  int s = 0;
+  while ((1LL << s) < chain_len) ++s;
+  d.chain_magic = (uint32_t)(((uint64_t)1 << (31 + s)) / (uint64_t)chain_len + 1);
+  d.chain_shift = s - 1;
   return d;
 }
 

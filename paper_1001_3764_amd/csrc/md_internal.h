@@ -63,7 +63,16 @@ struct FFDev {
   double rc2;
   double kb, b0, ka, theta0, kphi, cos_phis, sin_phis;
   int32_t n_dih, excl, chain_len, uniform_lj;
+  // i / chain_len = umulhi(i, chain_magic) >> chain_shift for 0 <= i < 2^25 (chain_len >= 4):
+  // chain_magic = floor(2^(31 + s) / chain_len) + 1, chain_shift = s - 1, s = ceil(log2 chain_len)
+  uint32_t chain_magic;
+  int32_t chain_shift;
 };
+
+// First atom of atom i's chain, i - i % chain_len, without an integer division.
+__device__ inline int32_t chain_first(int32_t i, const FFDev& ff) {
+  return (int32_t)(__umulhi((uint32_t)i, ff.chain_magic) >> ff.chain_shift) * ff.chain_len;
+}
 
 // double-double accumulator (sum and the rounding error carried alongside)
 struct dd {

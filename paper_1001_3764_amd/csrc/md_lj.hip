@@ -226,7 +226,7 @@ __global__ __launch_bounds__(kLjAtomBlock) void k_lj_atom(Views v, FFDev ff, LjP
     const int32_t tag = pay_tag(pi);
     const int32_t i = tag_index(tag);
     const int ti = tag_type(tag);
-    const int32_t cs = i - i % ff.chain_len;
+    const int32_t cs = chain_first(i, ff);
     const int32_t lo = max(i - ff.excl, cs);
     const int32_t hi = min(i + ff.excl, cs + ff.chain_len - 1);
     const uint32_t span = (uint32_t)(hi - lo);
@@ -591,7 +591,7 @@ void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
           }
           const int32_t tag = FP64 ? uni(pay_tag(q)) : pay_tag(q);
           const int32_t i = tag_index(tag);
-          const int32_t c0 = i - i % ff.chain_len;
+          const int32_t c0 = chain_first(i, ff);
           lo[k] = max(i - ff.excl, c0);
           span[k] = (uint32_t)(min(i + ff.excl, c0 + ff.chain_len - 1) - lo[k]);
           hti[k] = tag_type(tag);
@@ -776,7 +776,7 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_nl_build(Views v, FFDev ff)
         hy[k] = uni(q.y);
         hz[k] = uni(q.z);
         const int32_t i = tag_index(uni(pay_tag(q)));
-        const int32_t c0 = i - i % ff.chain_len;
+        const int32_t c0 = chain_first(i, ff);
         lo[k] = max(i - ff.excl, c0);
         span[k] = (uint32_t)(min(i + ff.excl, c0 + ff.chain_len - 1) - lo[k]);
       } else {
