@@ -297,6 +297,7 @@ __global__ __launch_bounds__(kLjAtomBlock) void k_lj_atom(Views v, FFDev ff, LjP
 // array of candidates in LDS (sorted-array index << 7 | stencil offset code), and streams
 // that list 64 lanes at a time against up to KMAX home atoms held wave-uniform.
 constexpr int kListCap = 1024;   // candidates a wave lists at a time
+static_assert(kListCap / 64 <= 32, "the list build keeps one bit per 64-candidate step");
 constexpr int kMaxStencil = (2 * kTileMaxR + 1) * (2 * kTileMaxR + 1) * (2 * kTileMaxR + 1);
 static_assert(kMaxStencil <= 128, "stencil code must fit 7 bits");
 
@@ -881,6 +882,7 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_nl_build_tile(Views v, FFDe
   const float rl2s = (float)(rl2 * kFix * kFix);
   const int cap = v.nl_cap;
   uint32_t* __restrict__ out = v.nl_list + B.nl_off + (int64_t)lc * cap;
+  constexpr int KB = FP64 ? 4 : 8;   // homes held in registers at a time
   int cnt = 0;
   for (int c0 = 0; c0 < total; c0 += kListCap) {
     if (c0 != resident) {
@@ -888,32 +890,48 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_nl_build_tile(Views v, FFDe
       resident = c0;
     }
     const int cn = min(kListCap, total - c0);
-    for (int t0 = 0; t0 < cn; t0 += 64) {
-      const bool act = t0 + ln < cn;
-      uint32_t ent = 0;
-      Q jx = (Q)0, jy = (Q)0, jz = (Q)0;
-      if (act) {
-        ent = list[wave][t0 + ln];
-        const PayT q = pay[ent >> 7];
-        const Shift<Q> sh = shifts[ent & 127];
-        jx = q.x + sh.x;
-        jy = q.y + sh.y;
-        jz = q.z + sh.z;
-      }
-      bool hit = false;
-      for (int h = 0; h < hn; ++h) {
-        const PayT q = pay[hs + h];
-        if constexpr (FP64) {
-          const double dx = q.x - jx, dy = q.y - jy, dz = q.z - jz;
-          hit = hit || dx * dx + dy * dy + dz * dz < rl2;
-        } else {
-          hit = hit || r2_fix((float)(q.x - jx), (float)(q.y - jy), (float)(q.z - jz)) < rl2s;
+    // bit s: the candidate of step s (list position c0 + 64 s + lane) is within reach of a home
+    uint32_t hits = 0;
+    for (int g0 = 0; g0 < hn; g0 += KB) {
+      const int kc = min(KB, hn - g0);
+      Q hx[KB], hy[KB], hz[KB];
+#pragma unroll
+      for (int k = 0; k < KB; ++k) {
+        hx[k] = hy[k] = hz[k] = (Q)0;
+        if (k < kc) {
+          const PayT q = pay[hs + g0 + k];
+          hx[k] = q.x;
+          hy[k] = q.y;
+          hz[k] = q.z;
         }
       }
-      hit = hit && act;
+      for (int t0 = 0, s = 0; t0 < cn; t0 += 64, ++s) {
+        if (t0 + ln >= cn) continue;
+        const uint32_t ent = list[wave][t0 + ln];
+        const PayT q = pay[ent >> 7];
+        const Shift<Q> sh = shifts[ent & 127];
+        const Q jx = q.x + sh.x, jy = q.y + sh.y, jz = q.z + sh.z;
+        bool hit = false;
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+          if (k < kc) {
+            if constexpr (FP64) {
+              const double dx = hx[k] - jx, dy = hy[k] - jy, dz = hz[k] - jz;
+              hit = hit || dx * dx + dy * dy + dz * dz < rl2;
+            } else {
+              hit = hit || r2_fix((float)(hx[k] - jx), (float)(hy[k] - jy), (float)(hz[k] - jz)) < rl2s;
+            }
+          }
+        }
+        if (hit) hits |= 1u << s;
+      }
+    }
+    // compaction in list order
+    for (int t0 = 0, s = 0; t0 < cn; t0 += 64, ++s) {
+      const bool hit = (hits >> s) & 1u;
       const uint64_t m = __ballot(hit);
       const int at = cnt + lanes_below(m);
-      if (hit && at < cap) out[at] = ent;
+      if (hit && at < cap) out[at] = list[wave][t0 + ln];
       cnt += __popcll(m);
     }
   }
