@@ -41,6 +41,123 @@ __device__ inline int lanes_below(uint64_t m) {
   return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
+// ---------------------------------------------------------------------------------
+// Cross-lane exchanges that need no lane-address register.  A shuffle through
+// ds_bpermute takes a per-lane byte address; the compiler computes those once and
+// keeps them live for the whole kernel (one register per distinct pattern), which in
+// the tile kernel pushed values out to scratch.  These use gfx950's 32- and 16-lane
+// row swaps and DPP moves within 16-lane rows, so only the data travels.
+//
+// Swaps: after v_permlane32_swap(a, b) lanes 32-63 of a hold lanes 0-31 of b and lanes
+// 0-31 of b hold lanes 32-63 of a; v_permlane16_swap does the same between the odd
+// 16-lane rows of a and the even rows of b.  DPP: row_ror:8 reads lane l ^ 8 (rotation
+// by half of a 16-lane row), row_half_mirror lane l ^ 7, quad_perm [2,3,0,1] lane l ^ 2
+// and [1,0,3,2] lane l ^ 1.
+
+enum class Xl { Swap32, Swap16, Ror8, Mirror8, Quad2, Quad1 };
+
+__device__ __forceinline__ uint32_t dpp32(uint32_t x, Xl p) {
+  switch (p) {
+    case Xl::Ror8: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x128, 0xf, 0xf, false);
+    case Xl::Mirror8: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x141, 0xf, 0xf, false);
+    case Xl::Quad2: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4e, 0xf, 0xf, false);
+    default: return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xb1, 0xf, 0xf, false);
+  }
+}
+
+// Lanes below the split (l & 32, or l & 16, clear) get a[l] and a[partner]; lanes above
+// get b[partner] and b[l].  Returned as {first, second}: first + second is the pair sum
+// each side keeps.
+__device__ __forceinline__ void swap32(uint32_t a, uint32_t b, Xl p, uint32_t& first, uint32_t& second) {
+  if (p == Xl::Swap32) {
+    const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+    first = r[0];
+    second = r[1];
+  } else {
+    const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+    first = r[0];
+    second = r[1];
+  }
+}
+
+template <typename T>
+struct XlBits;
+template <>
+struct XlBits<float> {
+  static constexpr int n = 1;
+  __device__ static void split(float x, uint32_t* w) { w[0] = __float_as_uint(x); }
+  __device__ static float join(const uint32_t* w) { return __uint_as_float(w[0]); }
+};
+template <>
+struct XlBits<double> {
+  static constexpr int n = 2;
+  __device__ static void split(double x, uint32_t* w) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    w[0] = (uint32_t)b;
+    w[1] = (uint32_t)(b >> 32);
+  }
+  __device__ static double join(const uint32_t* w) {
+    return __longlong_as_double((long long)(((unsigned long long)w[1] << 32) | w[0]));
+  }
+};
+template <>
+struct XlBits<int> {
+  static constexpr int n = 1;
+  __device__ static void split(int x, uint32_t* w) { w[0] = (uint32_t)x; }
+  __device__ static int join(const uint32_t* w) { return (int)w[0]; }
+};
+
+// Sum kept by each side of a swap exchange: lanes below the split get a[l] + a[partner],
+// lanes above b[partner] + b[l] (the halving step of a reduction of two value sets).
+template <typename T>
+__device__ __forceinline__ T swap_sum(T a, T b, Xl p) {
+  uint32_t wa[XlBits<T>::n], wb[XlBits<T>::n], f[XlBits<T>::n], s[XlBits<T>::n];
+  XlBits<T>::split(a, wa);
+  XlBits<T>::split(b, wb);
+#pragma unroll
+  for (int i = 0; i < XlBits<T>::n; ++i) swap32(wa[i], wb[i], p, f[i], s[i]);
+  return XlBits<T>::join(f) + XlBits<T>::join(s);
+}
+
+// The value of x on the partner lane (l ^ 32, l ^ 16, l ^ 8, l ^ 7, l ^ 2 or l ^ 1).
+template <typename T>
+__device__ __forceinline__ T partner(T x, Xl p) {
+  uint32_t w[XlBits<T>::n], o[XlBits<T>::n];
+  XlBits<T>::split(x, w);
+  if (p == Xl::Swap32 || p == Xl::Swap16) {
+    const bool above = (lane() & (p == Xl::Swap32 ? 32 : 16)) != 0;
+#pragma unroll
+    for (int i = 0; i < XlBits<T>::n; ++i) {
+      uint32_t f, s;
+      swap32(w[i], w[i], p, f, s);
+      o[i] = above ? f : s;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < XlBits<T>::n; ++i) o[i] = dpp32(w[i], p);
+  }
+  return XlBits<T>::join(o);
+}
+
+// x + x[l ^ mask]; both lanes of a pair add the same two values, so they agree bitwise.
+template <typename T>
+__device__ __forceinline__ T pair_add(T x, Xl p) {
+  if (p == Xl::Swap32 || p == Xl::Swap16) return swap_sum(x, x, p);
+  return x + partner(x, p);
+}
+
+// The butterfly patterns from the widest down; masks 32, 16, 8, 7, 2, 1 span all six
+// lane bits, so after levels [from, 6) every lane of a 2^(6 - from)-lane group holds the
+// group's sum (the same value on each).
+constexpr Xl kLevel[6] = {Xl::Swap32, Xl::Swap16, Xl::Ror8, Xl::Mirror8, Xl::Quad2, Xl::Quad1};
+
+template <typename T>
+__device__ __forceinline__ T group_sum(T x, int from) {
+#pragma unroll
+  for (int lv = from; lv < 6; ++lv) x = pair_add(x, kLevel[lv]);
+  return x;
+}
+
 // Relative half-width of the band around rc^2 decided in FP64 (well above the FP32 error
 // of r^2 from exact fixed-point differences, ~3e-7, plus the 2^-26 A position rounding).
 constexpr double kBand = 1e-6;
@@ -187,10 +304,8 @@ template <int NW>
 __device__ void block_energy(double e, double es, double w, dd (*red)[3], dd* out) {
   dd q[3] = {dd_from(0.5 * e), dd_from(0.5 * es), dd_from(0.5 * w)};
   for (int k = 0; k < 3; ++k)
-    for (int off = 32; off > 0; off >>= 1) {
-      dd o{__shfl_xor(q[k].hi, off), __shfl_xor(q[k].lo, off)};
-      q[k] = dd_add(q[k], o);
-    }
+#pragma unroll
+    for (int lv = 0; lv < 6; ++lv) q[k] = dd_add(q[k], dd{partner(q[k].hi, kLevel[lv]), partner(q[k].lo, kLevel[lv])});
   if (lane() == 0)
     for (int k = 0; k < 3; ++k) red[threadIdx.x >> 6][k] = q[k];
   __syncthreads();
@@ -306,15 +421,18 @@ struct Shift {
   Q x, y, z;   // stencil offset (ox, oy, oz) times the cell edge, in the payload's units
 };
 
+// Exclusive prefix sum of x >= 0 over the wave, bit plane by bit plane: the lanes below
+// this one whose bit b is set add 2^b each (a ballot and a masked popcount per plane).
 __device__ __forceinline__ int wave_exclusive_scan(int x, int& total) {
-  const int ln = lane();
-  int s = x;
-  for (int d = 1; d < 64; d <<= 1) {
-    const int y = __shfl_up(s, d);
-    if (ln >= d) s += y;
+  int below = 0, tot = 0;
+  for (int b = 0; b < 31; ++b) {
+    if (__ballot((x >> b) != 0) == 0) break;
+    const uint64_t m = __ballot((x >> b) & 1);
+    below += lanes_below(m) << b;
+    tot += __popcll(m) << b;
   }
-  total = __shfl(s, 63);
-  return s - x;
+  total = tot;
+  return below;
 }
 
 // Writes entries [c0, c0 + kListCap) of home cell lc's candidate list to list[]; returns
@@ -381,11 +499,11 @@ struct BandEnergy {
 // their band pairs queued in (step, home, lane) order, refilling the list where a step lies
 // in another chunk; each queued pair is then re-decided in FP64 and, when outside, taken
 // back out of the stored force of its home (summed per home over the lanes, applied by the
-// lane that stored that home).  With more steps or pairs than the slots hold (not
-// expected in a melt) every candidate of the group is walked again instead.  LDS executes
-// a wave's accesses in order and only this wave wrote its slots, so no barrier is needed.
-// `resident` is the chunk the list holds; it is updated.
-template <bool ENERGY, bool UNI, bool LIST>
+// lane that stored that home: lane k << SHIFT for home k).  With more steps or pairs than
+// the slots hold (not expected in a melt) every candidate of the group is walked again
+// instead.  LDS executes a wave's accesses in order and only this wave wrote its slots,
+// so no barrier is needed.  `resident` is the chunk the list holds; it is updated.
+template <bool ENERGY, bool UNI, bool LIST, int SHIFT>
 __device__ __forceinline__ BandEnergy settle_band_group(const Views& v, int chain_len, int excl, double rc2,
                                                         const LjPair<float>& cf, const BoxDev& B, Band bd, int lc,
                                                         int total, uint32_t* list, int& resident,
@@ -457,12 +575,10 @@ __device__ __forceinline__ BandEnergy settle_band_group(const Views& v, int chai
     for (int k = 0; k < kc; ++k) {
       if (__ballot(kq == k) == 0) continue;
       float sx = kq == k ? bx : 0.0f, sy = kq == k ? by : 0.0f, sz = kq == k ? bz : 0.0f;
-      for (int off = 32; off > 0; off >>= 1) {
-        sx += __shfl_xor(sx, off);
-        sy += __shfl_xor(sy, off);
-        sz += __shfl_xor(sz, off);
-      }
-      if (ln == k) {
+      sx = group_sum(sx, 0);
+      sy = group_sum(sy, 0);
+      sz = group_sum(sz, 0);
+      if (ln == k << SHIFT) {
         const int32_t i = tag_index(pay_tag(pay[hs + g0 + k]));
         f[i] += sx * kInvFixF;
         f[v.N + i] += sy * kInvFixF;
@@ -498,12 +614,10 @@ __device__ __forceinline__ BandEnergy settle_band_group(const Views& v, int chai
           }
         }
       }
-      for (int off = 32; off > 0; off >>= 1) {
-        bx += __shfl_xor(bx, off);
-        by += __shfl_xor(by, off);
-        bz += __shfl_xor(bz, off);
-      }
-      if (ln == k) {
+      bx = group_sum(bx, 0);
+      by = group_sum(by, 0);
+      bz = group_sum(bz, 0);
+      if (ln == k << SHIFT) {
         f[i] += bx * kInvFixF;
         f[v.N + i] += by * kInvFixF;
         f[2 * v.N + i] += bz * kInvFixF;
@@ -524,6 +638,8 @@ void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
   using PayT = std::conditional_t<FP64, Pay64, int4>;
   using P = std::conditional_t<FP64, double, float>;
   using Q = std::conditional_t<FP64, double, int>;     // coordinate type
+  constexpr int LV = KMAX == 8 ? 3 : (KMAX == 4 ? 2 : (KMAX == 2 ? 1 : 0));   // log2(KMAX)
+  static_assert((1 << LV) == KMAX, "KMAX must be 1, 2, 4 or 8");
   __shared__ uint32_t list[kTileWaves][kListCap];
   __shared__ Shift<Q> shifts[kMaxStencil];
   __shared__ dd red[kTileWaves][3];
@@ -656,12 +772,10 @@ void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
       // halving: at each of the first log2(KMAX) levels a lane keeps half of its values and
       // adds the partner's copy of that half, so the 3 KMAX sums take 3 KMAX - 3 exchanges
       // (instead of 18 KMAX for separate butterflies); then a butterfly over the remaining
-      // lanes, after which lanes [h * 64/KMAX, (h + 1) * 64/KMAX) hold home h's sums, and lane
-      // k fetches home k's (the lane that stores a home also applies its band corrections).
+      // lane bits, after which lanes [h * 64/KMAX, (h + 1) * 64/KMAX) hold home h's sums
+      // and the first of them stores it (and later applies its band corrections).
       P* f = static_cast<P*>(v.f_lj);
       {
-        constexpr int LV = KMAX == 8 ? 3 : (KMAX == 4 ? 2 : (KMAX == 2 ? 1 : 0));
-        static_assert((1 << LV) == KMAX, "KMAX must be 1, 2, 4 or 8");
         constexpr int NV = 3 * KMAX;
         P val[NV];
 #pragma unroll
@@ -672,29 +786,31 @@ void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
         }
 #pragma unroll
         for (int lv = 0; lv < LV; ++lv) {
-          const int off = 32 >> lv;
-          const bool hi = (ln & off) != 0;
 #pragma unroll
           for (int i = 0; i < (NV >> lv) / 2; ++i) {
             const int h = (NV >> lv) / 2 + i;
-            const P send = hi ? val[i] : val[h];
-            const P keep = hi ? val[h] : val[i];
-            val[i] = keep + __shfl_xor(send, off);
+            if (lv < 2) {
+              // lanes below the split keep val[i], those above val[h]
+              val[i] = swap_sum(val[i], val[h], kLevel[lv]);
+            } else {
+              const bool hi = (ln & 8) != 0;
+              const P send = hi ? val[i] : val[h];
+              const P keep = hi ? val[h] : val[i];
+              val[i] = keep + partner(send, Xl::Ror8);
+            }
           }
         }
 #pragma unroll
-        for (int lv = LV; lv < 6; ++lv)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) val[c] += __shfl_xor(val[c], 32 >> lv);
-        const int src = (ln & (KMAX - 1)) << (6 - LV);
-        P sx = __shfl(val[0], src), sy = __shfl(val[1], src), sz = __shfl(val[2], src);
+        for (int c = 0; c < 3; ++c) val[c] = group_sum(val[c], LV);
+        P sx = val[0], sy = val[1], sz = val[2];
         if constexpr (!FP64) {
           sx *= fscale;
           sy *= fscale;
           sz *= fscale;
         }
-        if (ln < kc) {
-          const int32_t i = tag_index(pay_tag(pay[hs + g0 + ln]));
+        const int hk = ln >> (6 - LV);
+        if ((ln & ((64 >> LV) - 1)) == 0 && hk < kc) {
+          const int32_t i = tag_index(pay_tag(pay[hs + g0 + hk]));
           f[i] = sx;
           f[v.N + i] = sy;
           f[2 * v.N + i] = sz;
@@ -702,7 +818,7 @@ void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
       }
       if constexpr (!FP64) {
         if (nsteps > 0) {
-          const BandEnergy be = settle_band_group<ENERGY, UNI, LIST>(v, ff.chain_len, ff.excl, ff.rc2, cf, B, bd, lc,
+          const BandEnergy be = settle_band_group<ENERGY, UNI, LIST, 6 - LV>(v, ff.chain_len, ff.excl, ff.rc2, cf, B, bd, lc,
                                                                total, list[wave], resident, shifts, bsteps[wave],
                                                                bq[wave], pay, hs, g0, kc, nsteps);
           if (ENERGY) {
