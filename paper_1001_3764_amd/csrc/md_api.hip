@@ -196,6 +196,8 @@ Plan make_plan(const md_forcefield* ff, const md_config* cfg, int R, int kernel)
       B.edge_q[d] = (int32_t)std::lrint(B.edge[d] * kFix);
       nc *= M;
     }
+    B.inv_mx = 1.0 / (double)B.M[0];
+    B.inv_mxy = 1.0 / ((double)B.M[0] * (double)B.M[1]);
     B.atom_off = (int32_t)atom;
     B.n_atoms = (int32_t)n;
     B.cell_off = (int32_t)cell;

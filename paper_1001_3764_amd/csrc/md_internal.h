@@ -40,6 +40,7 @@ struct BoxDev {
   double edge[3];         // L/M
   int32_t M[3];
   int32_t edge_q[3];      // cell edge in fixed-point units (rint(edge * 2^25))
+  double inv_mx, inv_mxy; // 1 / M[0] and 1 / (M[0] M[1]) (cell_coords)
   int32_t atom_off, n_atoms;
   int32_t cell_off, n_cells;
   int32_t blk_off;        // first per-atom block (kAtomBlock) of this box
@@ -72,6 +73,32 @@ struct FFDev {
 // First atom of atom i's chain, i - i % chain_len, without an integer division.
 __device__ inline int32_t chain_first(int32_t i, const FFDev& ff) {
   return (int32_t)(__umulhi((uint32_t)i, ff.chain_magic) >> ff.chain_shift) * ff.chain_len;
+}
+
+// Cell coordinates (lc % M0, lc / M0 % M1, lc / (M0 M1)) of cell lc of box B, without
+// integer division: (lc + 1/2) / M lies at least 1/(2M) from an integer, and the FP64
+// product with the rounded reciprocal errs by about 2^-51 times the quotient, which is
+// below that margin while the box has fewer than 2^50 cells.
+struct Cell3 {
+  int x, y, z;
+};
+__device__ inline Cell3 cell_coords(int lc, const BoxDev& B) {
+  const double a = (double)lc + 0.5;
+  const int qy = (int)(a * B.inv_mx);    // lc / M0
+  const int qz = (int)(a * B.inv_mxy);   // lc / (M0 M1)
+  return Cell3{lc - qy * B.M[0], qy - qz * B.M[1], qz};
+}
+
+// Offsets (ox, oy, oz) in [-R, R] of stencil code = (ox + R) + W ((oy + R) + W (oz + R)),
+// W = 2R + 1, for 0 <= code < W^3 and W <= 15: the quotients by W and W^2 come from FP32
+// products with v_rcp_f32 reciprocals (1 ulp); (code + 1/2) / W^k lies at least 1/(2 W^2)
+// from an integer, far above the products' error (< 1e-4).
+__device__ inline Cell3 stencil_offset(int code, int R) {
+  const int W = 2 * R + 1;
+  const float a = (float)code + 0.5f;
+  const int q1 = (int)(a * __builtin_amdgcn_rcpf((float)W));
+  const int q2 = (int)(a * __builtin_amdgcn_rcpf((float)(W * W)));
+  return Cell3{code - q1 * W - R, q1 - q2 * W - R, q2 - R};
 }
 
 // double-double accumulator (sum and the rounding error carried alongside)

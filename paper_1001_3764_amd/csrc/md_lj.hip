@@ -347,7 +347,8 @@ __global__ __launch_bounds__(kLjAtomBlock) void k_lj_atom(Views v, FFDev ff, LjP
     const uint32_t span = (uint32_t)(hi - lo);
     const int c = v.scell[s] - B.cell_off;
     const int M0 = B.M[0], M1 = B.M[1], M2 = B.M[2];
-    const int kx = c % M0, ky = (c / M0) % M1, kz = c / (M0 * M1);
+    const Cell3 k3 = cell_coords(c, B);
+    const int kx = k3.x, ky = k3.y, kz = k3.z;
     P fx = 0, fy = 0, fz = 0;
     for (int oz = -R; oz <= R; ++oz) {
       int nz = kz + oz;
@@ -442,7 +443,7 @@ __device__ __forceinline__ int fill_list(const Views& v, const BoxDev& B, int lc
   const int ln = lane();
   const int R = v.R, W = 2 * R + 1, W3 = W * W * W;
   const int M0 = B.M[0], M1 = B.M[1], M2 = B.M[2];
-  const int kx = lc % M0, ky = (lc / M0) % M1, kz = lc / (M0 * M1);
+  const Cell3 k3 = cell_coords(lc, B);
   int start[2], n[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
@@ -450,7 +451,8 @@ __device__ __forceinline__ int fill_list(const Views& v, const BoxDev& B, int lc
     start[h] = 0;
     n[h] = 0;
     if (code < W3) {
-      int nx = kx + code % W - R, ny = ky + (code / W) % W - R, nz = kz + code / (W * W) - R;
+      const Cell3 o = stencil_offset(code, R);
+      int nx = k3.x + o.x, ny = k3.y + o.y, nz = k3.z + o.z;
       nx += nx < 0 ? M0 : 0;
       nx -= nx >= M0 ? M0 : 0;
       ny += ny < 0 ? M1 : 0;
@@ -665,7 +667,8 @@ void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
     const int R = v.R, W = 2 * R + 1;
     const int code = (int)threadIdx.x;
     if (code < W * W * W) {
-      const int ox = code % W - R, oy = (code / W) % W - R, oz = code / (W * W) - R;
+      const Cell3 o = stencil_offset(code, R);
+      const int ox = o.x, oy = o.y, oz = o.z;
       if constexpr (FP64)
         shifts[code] = Shift<Q>{ox * B.edge[0], oy * B.edge[1], oz * B.edge[2]};
       else
@@ -861,7 +864,8 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_nl_build(Views v, FFDev ff)
     const int R = v.R, W = 2 * R + 1;
     const int code = (int)threadIdx.x;
     if (code < W * W * W) {
-      const int ox = code % W - R, oy = (code / W) % W - R, oz = code / (W * W) - R;
+      const Cell3 o = stencil_offset(code, R);
+      const int ox = o.x, oy = o.y, oz = o.z;
       if constexpr (FP64)
         shifts[code] = Shift<Q>{ox * B.edge[0], oy * B.edge[1], oz * B.edge[2]};
       else
@@ -980,7 +984,8 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_nl_build_tile(Views v, FFDe
     const int R = v.R, W = 2 * R + 1;
     const int code = (int)threadIdx.x;
     if (code < W * W * W) {
-      const int ox = code % W - R, oy = (code / W) % W - R, oz = code / (W * W) - R;
+      const Cell3 o = stencil_offset(code, R);
+      const int ox = o.x, oy = o.y, oz = o.z;
       if constexpr (FP64)
         shifts[code] = Shift<Q>{ox * B.edge[0], oy * B.edge[1], oz * B.edge[2]};
       else
@@ -1075,7 +1080,8 @@ __global__ __launch_bounds__(kLjNlBlock) void k_lj_nl(Views v, FFDev ff, LjPair<
     const int R = v.R, W = 2 * R + 1;
     const int code = (int)threadIdx.x;
     if (code < W * W * W) {
-      const int ox = code % W - R, oy = (code / W) % W - R, oz = code / (W * W) - R;
+      const Cell3 o = stencil_offset(code, R);
+      const int ox = o.x, oy = o.y, oz = o.z;
       if constexpr (FP64)
         shifts[code] = Shift<Q>{ox * B.edge[0], oy * B.edge[1], oz * B.edge[2]};
       else

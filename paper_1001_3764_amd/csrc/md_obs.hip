@@ -47,11 +47,12 @@ __global__ __launch_bounds__(kAtomBlock) void k_obs_pairs(Views v, int b, int ch
        s += (int64_t)gridDim.x * kAtomBlock) {
     const int32_t i = v.cell_atoms[s];
     const int lc = v.scell[s] - B.cell_off;
-    const int kx = lc % M0, ky = (lc / M0) % M1, kz = lc / (M0 * M1);
+    const Cell3 k3 = cell_coords(lc, B);
     const double xi = v.pos[i], yi = v.pos[N + i], zi = v.pos[2 * N + i];
     const int32_t ci = i / chain_len;
     for (int code = 0; code < W * W * W; ++code) {
-      int nx = kx + code % W - R, ny = ky + (code / W) % W - R, nz = kz + code / (W * W) - R;
+      const Cell3 o = stencil_offset(code, R);
+      int nx = k3.x + o.x, ny = k3.y + o.y, nz = k3.z + o.z;
       nx += nx < 0 ? M0 : 0;
       nx -= nx >= M0 ? M0 : 0;
       ny += ny < 0 ? M1 : 0;
