@@ -413,6 +413,8 @@ __global__ __launch_bounds__(kLjAtomBlock) void k_lj_atom(Views v, FFDev ff, LjP
 // array of candidates in LDS (sorted-array index << 7 | stencil offset code), and streams
 // that list 64 lanes at a time against up to KMAX home atoms held wave-uniform.
 constexpr int kListCap = 1024;   // candidates a wave lists at a time
+constexpr int kCompacted = -2;   // `resident` when the list holds a home group's filtered candidates
+constexpr int kFilterSteps = 4;  // candidate steps the filter loads at once
 static_assert(kListCap / 64 <= 32, "the list build keeps one bit per 64-candidate step");
 constexpr int kMaxStencil = (2 * kTileMaxR + 1) * (2 * kTileMaxR + 1) * (2 * kTileMaxR + 1);
 static_assert(kMaxStencil <= 128, "stencil code must fit 7 bits");
@@ -503,12 +505,14 @@ struct BandEnergy {
 // back out of the stored force of its home (summed per home over the lanes, applied by the
 // lane that stored that home: lane k << SHIFT for home k).  With more steps or pairs than
 // the slots hold (not expected in a melt) every candidate of the group is walked again
-// instead.  LDS executes a wave's accesses in order and only this wave wrote its slots,
-// so no barrier is needed.  `resident` is the chunk the list holds; it is updated.
+// instead, from the full list (total entries).  LDS executes a wave's accesses in order
+// and only this wave wrote its slots, so no barrier is needed.  `resident` is the chunk
+// the list holds, or kCompacted when it holds the group's ncand filtered candidates (the
+// positions the steps were recorded at); it is updated.
 template <bool ENERGY, bool UNI, bool LIST, int SHIFT>
 __device__ __forceinline__ BandEnergy settle_band_group(const Views& v, int chain_len, int excl, double rc2,
                                                         const LjPair<float>& cf, const BoxDev& B, Band bd, int lc,
-                                                        int total, uint32_t* list, int& resident,
+                                                        int total, int ncand, uint32_t* list, int& resident,
                                                         const Shift<int>* shifts, const int* steps, int32_t* bq,
                                                         const int4* __restrict__ pay, int hs, int g0, int kc,
                                                         int nsteps) {
@@ -539,13 +543,13 @@ __device__ __forceinline__ BandEnergy settle_band_group(const Views& v, int chai
     for (int s = 0; s < nsteps; ++s) {
       const int fs = steps[s];
       const int c0 = fs - fs % kListCap;
-      if (c0 != resident) {
+      if (resident != kCompacted && c0 != resident) {
         load_list<LIST>(v, B, lc, c0, list);
         resident = c0;
       }
       int jx, jy, jz;
       int32_t jt;
-      const bool act = candidate(fs - c0 + ln, min(kListCap, total - c0), jx, jy, jz, jt);
+      const bool act = candidate(fs - c0 + ln, min(kListCap, ncand - c0), jx, jy, jz, jt);
       for (int k = 0; k < kc; ++k) {
         const int4 hq = pay[hs + g0 + k];
         int32_t hlo;
@@ -722,14 +726,74 @@ void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
           hti[k] = 0;
         }
       }
+      // Cell path with a one-chunk list: keep only the candidates within the cutoff of the
+      // box bounding the group's homes (about half of the stencil's atoms in a melt),
+      // compacted in place.  Per axis |x - clamp(x, lo, hi)| <= |x - x_home| for every home
+      // in the box, and each rounding is monotone, so the filter's r^2 (the pair test's
+      // own operation order in the mixed form) never exceeds a pair's: no counted pair is
+      // dropped.  Each step's reads precede its writes and land at or above them.
+      int ncand = total;    // list entries the step loop walks
+      if (!LIST && total <= kListCap) {
+        if (resident != 0) {
+          load_list<LIST>(v, B, lc, 0, list[wave]);
+          resident = 0;
+        }
+        Q lox = hx[0], hix = hx[0], loy = hy[0], hiy = hy[0], loz = hz[0], hiz = hz[0];
+#pragma unroll
+        for (int k = 1; k < KMAX; ++k)
+          if (k < kc) {
+            lox = min(lox, hx[k]);
+            hix = max(hix, hx[k]);
+            loy = min(loy, hy[k]);
+            hiy = max(hiy, hy[k]);
+            loz = min(loz, hz[k]);
+            hiz = max(hiz, hz[k]);
+          }
+        const double rc2_keep = ff.rc2 * (1.0 + 1e-12);
+        int m = 0;
+        // kFilter steps per batch with their loads in flight together (lanes past the end
+        // load entry 0, a valid payload index and stencil code, and are masked out); a
+        // batch reads all its entries before it writes any
+        constexpr int kFilter = FP64 ? 2 : kFilterSteps;
+        for (int t0 = 0; t0 < total; t0 += 64 * kFilter) {
+          uint32_t ent[kFilter];
+          Q jx[kFilter], jy[kFilter], jz[kFilter];
+#pragma unroll
+          for (int u = 0; u < kFilter; ++u) ent[u] = t0 + 64 * u + ln < total ? list[wave][t0 + 64 * u + ln] : 0u;
+#pragma unroll
+          for (int u = 0; u < kFilter; ++u) {
+            const PayT q = pay[ent[u] >> 7];
+            const Shift<Q> sh = shifts[ent[u] & 127];
+            jx[u] = q.x + sh.x;
+            jy[u] = q.y + sh.y;
+            jz[u] = q.z + sh.z;
+          }
+#pragma unroll
+          for (int u = 0; u < kFilter; ++u) {
+            const Q dx = jx[u] - min(max(jx[u], lox), hix), dy = jy[u] - min(max(jy[u], loy), hiy),
+                    dz = jz[u] - min(max(jz[u], loz), hiz);
+            bool pass;
+            if constexpr (FP64)
+              pass = dx * dx + dy * dy + dz * dz < rc2_keep;
+            else
+              pass = r2_fix((float)dx, (float)dy, (float)dz) < bd.hi;
+            pass = pass && t0 + 64 * u + ln < total;
+            const uint64_t bm = __ballot(pass);
+            if (pass) list[wave][m + lanes_below(bm)] = ent[u];
+            m += __popcll(bm);
+          }
+        }
+        ncand = m;
+        resident = kCompacted;
+      }
       int nsteps = 0;       // candidate steps with a band pair (wave-uniform)
       int32_t bmax = 0;     // bits of the largest r2s counted since the last band check
-      for (int c0 = 0; c0 < total; c0 += kListCap) {
-        if (c0 != resident) {
+      for (int c0 = 0; c0 < ncand; c0 += kListCap) {
+        if (resident != kCompacted && c0 != resident) {
           load_list<LIST>(v, B, lc, c0, list[wave]);
           resident = c0;
         }
-        const int cn = min(kListCap, total - c0);
+        const int cn = min(kListCap, ncand - c0);
         for (int t0 = 0; t0 < cn; t0 += 64) {
           const bool act = t0 + ln < cn;
           Q jx = (Q)0, jy = (Q)0, jz = (Q)0;
@@ -822,7 +886,7 @@ void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
       if constexpr (!FP64) {
         if (nsteps > 0) {
           const BandEnergy be = settle_band_group<ENERGY, UNI, LIST, 6 - LV>(v, ff.chain_len, ff.excl, ff.rc2, cf, B, bd, lc,
-                                                               total, list[wave], resident, shifts, bsteps[wave],
+                                                               total, ncand, list[wave], resident, shifts, bsteps[wave],
                                                                bq[wave], pay, hs, g0, kc, nsteps);
           if (ENERGY) {
             e += be.e;
