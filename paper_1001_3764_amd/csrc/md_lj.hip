@@ -429,8 +429,8 @@ struct Shift {
 __device__ __forceinline__ int wave_exclusive_scan(int x, int& total) {
   int below = 0, tot = 0;
   for (int b = 0; b < 31; ++b) {
-    if (__ballot((x >> b) != 0) == 0) break;
-    const uint64_t m = __ballot((x >> b) & 1);
+    if (__builtin_amdgcn_ballot_w64((x >> b) != 0) == 0) break;
+    const uint64_t m = __builtin_amdgcn_ballot_w64(((x >> b) & 1) != 0);
     below += lanes_below(m) << b;
     tot += __popcll(m) << b;
   }
@@ -557,7 +557,7 @@ __device__ __forceinline__ BandEnergy settle_band_group(const Views& v, int chai
         window(tag_index(pay_tag(hq)), hlo, hspan);
         const bool keep = act && (uint32_t)(tag_index(jt) - hlo) > hspan;
         const bool qb = in_band(r2_fix((float)(hq.x - jx), (float)(hq.y - jy), (float)(hq.z - jz)), keep, bd);
-        const uint64_t qm = __ballot(qb);
+        const uint64_t qm = __builtin_amdgcn_ballot_w64(qb);
         const int at = qn + lanes_below(qm);
         if (qb && at < kBandQueue) bq[at] = (tag_index(jt) << 4) | (tag_type(jt) << 3) | k;
         qn += __popcll(qm);
@@ -579,7 +579,7 @@ __device__ __forceinline__ BandEnergy settle_band_group(const Views& v, int chai
       }
     }
     for (int k = 0; k < kc; ++k) {
-      if (__ballot(kq == k) == 0) continue;
+      if (__builtin_amdgcn_ballot_w64(kq == k) == 0) continue;
       float sx = kq == k ? bx : 0.0f, sy = kq == k ? by : 0.0f, sz = kq == k ? bz : 0.0f;
       sx = group_sum(sx, 0);
       sy = group_sum(sy, 0);
@@ -778,7 +778,7 @@ void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
             else
               pass = r2_fix((float)dx, (float)dy, (float)dz) < bd.hi;
             pass = pass && t0 + 64 * u + ln < total;
-            const uint64_t bm = __ballot(pass);
+            const uint64_t bm = __builtin_amdgcn_ballot_w64(pass);
             if (pass) list[wave][m + lanes_below(bm)] = ent[u];
             m += __popcll(bm);
           }
@@ -1003,7 +1003,7 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_nl_build(Views v, FFDev ff)
               hit = r2_fix(dx, dy, dz) < rl2s;
             }
             hit = hit && act && (uint32_t)(jidx - lo[k]) > span[k];
-            const uint64_t m = __ballot(hit);
+            const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
             const int at = cnt[k] + lanes_below(m);
             if (hit && at < cap) {
               const int ls = hs + g0 + k - B.atom_off;   // box-local sorted slot of the home
@@ -1114,7 +1114,7 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_nl_build_tile(Views v, FFDe
     // compaction in list order
     for (int t0 = 0, s = 0; t0 < cn; t0 += 64, ++s) {
       const bool hit = (hits >> s) & 1u;
-      const uint64_t m = __ballot(hit);
+      const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
       const int at = cnt + lanes_below(m);
       if (hit && at < cap) out[at] = list[wave][t0 + ln];
       cnt += __popcll(m);
