@@ -288,7 +288,11 @@ def main():
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
                 "traffic": measured_traffic("%s/R%d/K%d" % (kname, R, kern)),
                 "kernel": "%s (Lennard-Jones, mixed, R=%d)" % (kname, R), "avg_launch_ms": round(lj_ms, 5),
-                "candidates_per_launch": cand, "pairs_per_launch": pairs, "flop_per_launch": flop}
+                "candidates_per_launch": cand, "pairs_per_launch": pairs, "flop_per_launch": flop,
+                "flop_basis": "8 flop per stencil candidate and home atom + 13 per pair inside the cutoff: the "
+                              "plain stencil algorithm's work"
+                              + ("; the cell tile's bounding-box filter sends about half of the candidates on "
+                                 "to the per-home test, so this is an effective rate" if kname == "k_lj_tile" else "")}
 
     # ---- force error of the mixed form against the FP64 oracle, at the grown melt and at the
     # state the timed run ended in (same positions on both sides) ----
