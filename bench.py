@@ -118,6 +118,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-nlist", action="store_true", help="skip the neighbour-list form")
     ap.add_argument("--no-leapfrog", action="store_true", help="skip the leap-frog + Nose-Hoover form")
+    ap.add_argument("--no-halfshell", action="store_true", help="skip the Newton-3 half-shell LJ form")
     ap.add_argument("--no-observables", action="store_true", help="skip the Section 5 observables")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first copy a device buffer of this many MiB (HBM counter calibration)")
@@ -278,6 +279,36 @@ def main():
         except Exception as exc:
             log("leapfrog run failed: %r" % (exc,))
 
+    # ---- Newton-3 half shell (opt-in kernel): each pair once, both forces added to int64
+    # fixed-point accumulators with device atomics; same grid, from the end-of-run state ----
+    halfshell = None
+    if not args.no_halfshell:
+        try:
+            from paper_1001_3764_amd.md import MD_LJ_HALFSHELL
+            sh = MDSystem(ff, [melt.n_chains], melt.box[None, :], [wl.T0[0]], pos_prof, vel_prof, melt.types,
+                          chain_len=wl.chain_len, dt=wl.dt_fs, tau=wl.tau_fs, precision="mixed", cell_div=R,
+                          lj_kernel=MD_LJ_HALFSHELL, use_graph=not args.no_graph, device=dev)
+            fh_lj = sh.forces(lj_only=True)
+            sh.step(20)
+            torch.cuda.synchronize(dev)
+            a = time.perf_counter()
+            n_hs = min(args.steps, 1000)
+            sh.step(n_hs)
+            torch.cuda.synchronize(dev)
+            b_ = time.perf_counter()
+            ph = {k: v / 50 for k, v in sh.step_timed(50).items()}
+            sh.close()
+            halfshell = {"value": N * n_hs / (b_ - a), "unit": "atom-steps/s", "steps": n_hs,
+                         "ms_per_step": 1e3 * (b_ - a) / n_hs, "lj_kernel": MD_LJ_HALFSHELL, "cell_div": R,
+                         "phases_ms_avg": {k: round(v, 5) for k, v in ph.items()},
+                         "lj_force_max_diff_vs_cell_path_over_frms": float(
+                             np.max(np.sqrt(np.sum((fh_lj - f_end_lj) ** 2, axis=0)))
+                             / np.sqrt(np.mean(np.sum(f_end ** 2, axis=0))))}
+            log("half shell: %.3f ms/step, %.3e atom-steps/s (LJ %.3f ms)" %
+                (halfshell["ms_per_step"], halfshell["value"], ph["lj"]))
+        except Exception as exc:
+            log("half-shell run failed: %r" % (exc,))
+
     cand, pairs = candidate_and_pair_counts(pos_prof, melt.box, start_prof, M, R, ff["rc"], melt.n_chains,
                                             melt.chain_len)
     lj_ms = phase_avg["lj"]
@@ -378,6 +409,7 @@ def main():
         "cpu_baseline_1thread": cpu1,
         "nlist_form": nlist,
         "leapfrog_nh_form": leapfrog,
+        "halfshell_form": halfshell,
         "observables": observables,
     }
     print(json.dumps(out), flush=True)

@@ -75,9 +75,16 @@ typedef enum {
                             zeroed outside the cutoff instead of branching (mixed precision) */
   MD_LJ_NLIST = 4,       /* neighbour-list mode (nl_skin > 0): a Verlet list per atom, one lane
                             per atom walking it */
-  MD_LJ_NLIST_TILE = 5   /* neighbour-list mode: a list per cell (every atom within rc + skin of
+  MD_LJ_NLIST_TILE = 5,  /* neighbour-list mode: a list per cell (every atom within rc + skin of
                             any atom of the cell at the build), streamed by the cell-tile kernel
                             against the cell's atoms */
+  MD_LJ_HALFSHELL = 6    /* cell path, opt-in (never chosen by the autotuner): each pair evaluated
+                            once (Newton's third law; the paper's Section 4 names the doubled
+                            pair work of its per-atom kernels as an inefficiency), both forces
+                            added to int64 fixed-point accumulators with device atomics, so the
+                            sums are exact and order-independent.  Measured slower than the full
+                            shell on this device: the atomics cost more than the second
+                            evaluation they save */
 } md_lj_kernel;
 
 typedef enum {
@@ -122,8 +129,8 @@ typedef struct {
   int32_t cell_div;           /* R: cells of edge >= rc / R, (2R+1)^3 cells visited;
                                  1 = the paper's grid (edge >= cutoff), 2 = half cells;
                                  0 = chosen by the autotuner at init */
-  int32_t lj_kernel;          /* md_lj_kernel: 1..3 (cell path) or 4..5 (neighbour-list mode), or 0
-                                 for the autotuner */
+  int32_t lj_kernel;          /* md_lj_kernel: 1..3 or 6 (cell path) or 4..5 (neighbour-list mode),
+                                 or 0 for the autotuner (which never picks 6) */
   int32_t use_graph;          /* 1: md_step replays a captured hipGraph of the step */
   double nl_skin;             /* > 0: neighbour-list mode.  A Verlet list of the pairs closer
                                  than rc + nl_skin (A) is built from the bins, and the bins and

@@ -89,8 +89,8 @@ md_status validate(const md_forcefield* ff, const md_config* cfg, std::string* w
   if (cfg->precision != MD_PREC_FP64 && cfg->precision != MD_PREC_MIXED) { *why = "bad precision"; return MD_ERR_ARG; }
   if (cfg->cell_div < 0 || cfg->cell_div > 3) { *why = "cell_div must be 0..3"; return MD_ERR_ARG; }
   if (cfg->nl_skin > 0.0 ? !(cfg->lj_kernel == 0 || cfg->lj_kernel == MD_LJ_NLIST || cfg->lj_kernel == MD_LJ_NLIST_TILE)
-                         : (cfg->lj_kernel < 0 || cfg->lj_kernel > 3)) {
-    *why = "lj_kernel must be 0..3 (cell path) or 0, MD_LJ_NLIST, MD_LJ_NLIST_TILE (neighbour lists)";
+                         : !((cfg->lj_kernel >= 0 && cfg->lj_kernel <= 3) || cfg->lj_kernel == MD_LJ_HALFSHELL)) {
+    *why = "lj_kernel must be 0..3 or MD_LJ_HALFSHELL (cell path), or 0, MD_LJ_NLIST, MD_LJ_NLIST_TILE (neighbour lists)";
     return MD_ERR_ARG;
   }
   if (cfg->integrator != MD_INT_VERLET_BERENDSEN && cfg->integrator != MD_INT_LEAPFROG_NH) {
@@ -142,6 +142,7 @@ struct Plan {
   int32_t n_boxes = 0, n_atom_blocks = 0, n_lj_blocks = 0, n_tiles = 0;
   int32_t n_cell_blocks = 0, nl_cap = 0;   // neighbour-list mode
   int64_t nl_entries = 0;
+  bool half = false;                        // half-shell LJ: fixed-point force accumulators
   int prec = 0;
   std::vector<BoxDev> boxes;
 };
@@ -176,6 +177,7 @@ Plan make_plan(const md_forcefield* ff, const md_config* cfg, int R, int kernel)
   p.n_boxes = cfg->n_boxes;
   p.prec = cfg->precision;
   const bool nl = cfg->nl_skin > 0.0;
+  p.half = !nl && kernel == MD_LJ_HALFSHELL;
   if (nl) {
     if (kernel != MD_LJ_NLIST_TILE) kernel = MD_LJ_NLIST;
     p.nl_cap = nl_capacity(ff, cfg, R, kernel);
@@ -257,6 +259,7 @@ size_t carve(const Plan& p, char* base, Views* v) {
   t.payload = take(psz * (size_t)p.N);
   t.f_lj = take(3 * fsz * (size_t)p.N);
   t.f_tot = take(3 * fsz * (size_t)p.N);
+  if (p.half) t.f_acc = (unsigned long long*)take(24 * (size_t)p.N);
   t.scan_tiles = (int32_t*)take(4 * (size_t)p.n_tiles);
   t.part_lj = (dd*)take(sizeof(dd) * 3 * (size_t)p.n_lj_blocks);
   t.part_bd = (dd*)take(sizeof(dd) * kBdParts * (size_t)p.n_atom_blocks);
@@ -382,6 +385,7 @@ md_status configure(md_ctx* c, const md_config* cfg, int R, int kernel) {
     return st;
   launch_fill_i32(v.cnt, p.C, 0, c->stream);
   launch_fill_i32(v.err, 1, 0, c->stream);
+  if (v.f_acc) launch_fill_i32((int32_t*)v.f_acc, 6 * p.N, 0, c->stream);
   launch_fill_f64(v.energy, kEnergySlots * (int64_t)p.n_boxes, 0.0, c->stream);
   if ((st = check_launch(c, "clear workspace"))) return st;
   c->v = v;
@@ -539,9 +543,9 @@ md_status md_workspace_bytes(const md_forcefield* ff, const md_config* cfg, size
     if (cfg->cell_div && cfg->cell_div != R) continue;
     if (!cfg->cell_div && R > 2) continue;
     if (!grid_ok(ff, cfg, R)) continue;
-    for (int K = 1; K <= 5; ++K) {
-      if (cfg->lj_kernel && cfg->lj_kernel != K) continue;
-      if ((cfg->nl_skin > 0.0) != (K >= MD_LJ_NLIST)) continue;
+    for (int K = 1; K <= MD_LJ_HALFSHELL; ++K) {
+      if (cfg->lj_kernel ? cfg->lj_kernel != K : K == MD_LJ_HALFSHELL) continue;
+      if ((cfg->nl_skin > 0.0) != (K == MD_LJ_NLIST || K == MD_LJ_NLIST_TILE)) continue;
       if (K >= MD_LJ_CELLTILE && R > kTileMaxR) continue;
       best = std::max(best, carve(make_plan(ff, cfg, R, K), nullptr, nullptr));
       any = true;

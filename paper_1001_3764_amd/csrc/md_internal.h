@@ -135,6 +135,7 @@ struct Views {
   void* payload;       // [N] int4 fixed point (mixed) / double4 (fp64): cell-centre-relative xyz + tag
   void* f_lj;          // [3N] LJ force, prec
   void* f_tot;         // [3N] total force, prec
+  unsigned long long* f_acc;   // [3N] half-shell LJ force, int64 fixed point (2^-32 kcal/mol/A); zero between uses
   int32_t* scan_tiles; // [n_tiles]
   dd* part_lj;         // [n_lj_blocks * 3]: E_lj, E_lj_shifted, W_lj
   dd* part_bd;         // [n_atom_blocks * kBdParts]: E_b, E_a, E_d, W_b, KE, momentum xyz

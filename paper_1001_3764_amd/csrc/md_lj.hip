@@ -900,6 +900,280 @@ void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
   if (ENERGY) block_energy<kTileWaves>(e, es, w, red, v.part_lj + (int64_t)blk * 3);
 }
 
+// Sums KMAX per-lane force accumulators (three components each) over the 64 lanes in a
+// fixed order, as the cell tile does inline: recursive halving over the first log2(KMAX) lane
+// bits, then a butterfly over the rest.  Afterwards every lane of
+// [h * 64/KMAX, (h + 1) * 64/KMAX) holds accumulator h's sums.
+template <typename P, int KMAX>
+__device__ __forceinline__ void sum_homes(int ln, P (&ax)[KMAX], P (&ay)[KMAX], P (&az)[KMAX], P& sx, P& sy,
+                                          P& sz) {
+  constexpr int LV = KMAX == 8 ? 3 : (KMAX == 4 ? 2 : (KMAX == 2 ? 1 : 0));
+  static_assert((1 << LV) == KMAX, "KMAX must be 1, 2, 4 or 8");
+  constexpr int NV = 3 * KMAX;
+  P val[NV];
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    val[3 * k] = ax[k];
+    val[3 * k + 1] = ay[k];
+    val[3 * k + 2] = az[k];
+  }
+#pragma unroll
+  for (int lv = 0; lv < LV; ++lv) {
+#pragma unroll
+    for (int i = 0; i < (NV >> lv) / 2; ++i) {
+      const int h = (NV >> lv) / 2 + i;
+      if (lv < 2) {
+        val[i] = swap_sum(val[i], val[h], kLevel[lv]);
+      } else {
+        const bool hi = (ln & 8) != 0;
+        const P send = hi ? val[i] : val[h];
+        const P keep = hi ? val[h] : val[i];
+        val[i] = keep + partner(send, Xl::Ror8);
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) val[c] = group_sum(val[c], LV);
+  sx = val[0];
+  sy = val[1];
+  sz = val[2];
+}
+
+// ---------------------------------------------------------------------------------
+// Newton-3 half shell (MD_LJ_HALFSHELL, opt-in; the inefficiency Section 4 names in its
+// thread-per-atom kernels is that every pair is computed twice).  Each pair is evaluated once:
+// a home cell's wave lists its own atoms and the forward half of its stencil (codes above the
+// centre), and takes an in-cell pair only from the lower of the two sorted positions.  The
+// force on each candidate (the reaction, summed on its lane over the group's homes) and on
+// each home (summed over the lanes) are added to per-atom int64 fixed-point accumulators
+// (units of 2^-32 kcal/mol/A) with device atomics.  Integer sums do not depend on the order of
+// the additions, so the result is deterministic; k_half_finish turns the accumulators into the
+// force array and clears them for the next evaluation.  Band pairs are decided from the FP64
+// positions before they are counted.
+constexpr double kHalfFix = 4294967296.0;   // accumulator units per kcal/mol/A
+
+// List of home cell lc for the half shell, entries [c0, c0 + kListCap): lane 0 lists the home
+// cell (its atoms come first, at positions [0, hn)), lanes 1..(W^3 - 1)/2 the forward cells.
+__device__ __forceinline__ int fill_list_half(const Views& v, const BoxDev& B, int lc, int c0, uint32_t* list) {
+  const int ln = lane();
+  const int R = v.R, W = 2 * R + 1, W3 = W * W * W, ctr = (W3 - 1) / 2;
+  const int M0 = B.M[0], M1 = B.M[1], M2 = B.M[2];
+  const Cell3 k3 = cell_coords(lc, B);
+  const int code = ctr + ln;
+  int start = 0, n = 0;
+  if (code < W3) {
+    const Cell3 o = stencil_offset(code, R);
+    int nx = k3.x + o.x, ny = k3.y + o.y, nz = k3.z + o.z;
+    nx += nx < 0 ? M0 : 0;
+    nx -= nx >= M0 ? M0 : 0;
+    ny += ny < 0 ? M1 : 0;
+    ny -= ny >= M1 ? M1 : 0;
+    nz += nz < 0 ? M2 : 0;
+    nz -= nz >= M2 ? M2 : 0;
+    const int c = B.cell_off + nx + M0 * (ny + M1 * nz);
+    start = v.cell_start[c];
+    n = v.cell_start[c + 1] - start;
+  }
+  int total;
+  const int f = wave_exclusive_scan(n, total);
+  const int a1 = min(n, c0 + kListCap - f);
+  for (int a = max(0, c0 - f); a < a1; ++a) list[f + a - c0] = ((uint32_t)(start + a) << 7) | code;
+  return total;
+}
+
+// Adds x (in units of 1/scale kcal/mol/A) to an int64 fixed-point accumulator.
+__device__ __forceinline__ void deposit(unsigned long long* a, double x) {
+  atomicAdd(a, (unsigned long long)__double2ll_rn(x));
+}
+
+template <bool FP64, bool ENERGY>
+__global__ __launch_bounds__(64 * kTileWaves) void k_lj_half(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
+  using PayT = std::conditional_t<FP64, Pay64, int4>;
+  using P = std::conditional_t<FP64, double, float>;
+  using Q = std::conditional_t<FP64, double, int>;
+  constexpr int KMAX = FP64 ? 4 : 8;
+  constexpr int LV = FP64 ? 2 : 3;
+  __shared__ uint32_t list[kTileWaves][kListCap];
+  __shared__ Shift<Q> shifts[kMaxStencil];
+  __shared__ dd red[kTileWaves][3];
+
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const int ln = lane();
+  const int per_xcd = (int)gridDim.x / kXcds;
+  const int blk = ((int)blockIdx.x % kXcds) * per_xcd + (int)blockIdx.x / kXcds;
+  if (blk >= v.n_lj_blocks) return;
+  const BoxDev& B = v.boxes[v.lj_blk_box[blk]];
+  const int lc = (blk - B.lj_blk_off) * kTileWaves + wave;
+  const bool wact = lc < B.n_cells;
+  const PayT* __restrict__ pay = static_cast<const PayT*>(v.payload);
+  const int R = v.R, W = 2 * R + 1, ctr = (W * W * W - 1) / 2;
+  {
+    const int code = (int)threadIdx.x;
+    if (code < W * W * W) {
+      const Cell3 o = stencil_offset(code, R);
+      if constexpr (FP64)
+        shifts[code] = Shift<Q>{o.x * B.edge[0], o.y * B.edge[1], o.z * B.edge[2]};
+      else
+        shifts[code] = Shift<Q>{o.x * B.edge_q[0], o.y * B.edge_q[1], o.z * B.edge_q[2]};
+    }
+  }
+  int total = 0, resident = 0;
+  if (wact) total = __builtin_amdgcn_readfirstlane(fill_list_half(v, B, lc, 0, list[wave]));
+  __syncthreads();
+
+  double e = 0.0, es = 0.0, w = 0.0;
+  if (wact) {
+    const int hs = __builtin_amdgcn_readfirstlane(v.cell_start[B.cell_off + lc]);
+    const int hn = __builtin_amdgcn_readfirstlane(v.cell_start[B.cell_off + lc + 1]) - hs;
+    const Band bd = make_band(ff.rc2);
+    // accumulator units per unit of the lane sums: mixed sums are in 2^25 (fixed-point) units
+    const double scale = FP64 ? kHalfFix : kHalfFix * (double)kInvFixF;
+    unsigned long long* __restrict__ acc = v.f_acc;
+    const int64_t N = v.N;
+    for (int g0 = 0; g0 < hn; g0 += KMAX) {
+      const int kc = min(KMAX, hn - g0);
+      Q hx[KMAX], hy[KMAX], hz[KMAX];
+      int32_t lo[KMAX], hti[KMAX], hidx[KMAX];
+      uint32_t span[KMAX];
+      P ax[KMAX], ay[KMAX], az[KMAX];
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) {
+        ax[k] = ay[k] = az[k] = (P)0;
+        hx[k] = hy[k] = hz[k] = (Q)0;
+        lo[k] = hti[k] = hidx[k] = 0;
+        span[k] = 0xffffffffu;   // excludes every candidate
+        if (k < kc) {
+          const PayT q = pay[hs + g0 + k];
+          hx[k] = q.x;
+          hy[k] = q.y;
+          hz[k] = q.z;
+          const int32_t tag = pay_tag(q);
+          const int32_t i = tag_index(tag);
+          const int32_t c0 = chain_first(i, ff);
+          hidx[k] = i;
+          lo[k] = max(i - ff.excl, c0);
+          span[k] = (uint32_t)(min(i + ff.excl, c0 + ff.chain_len - 1) - lo[k]);
+          hti[k] = tag_type(tag);
+        }
+      }
+      for (int c0 = 0; c0 < total; c0 += kListCap) {
+        if (c0 != resident) {
+          fill_list_half(v, B, lc, c0, list[wave]);
+          resident = c0;
+        }
+        const int cn = min(kListCap, total - c0);
+        for (int t0 = 0; t0 < cn; t0 += 64) {
+          const bool act = t0 + ln < cn;
+          Q jx = (Q)0, jy = (Q)0, jz = (Q)0;
+          int32_t jt = 0;
+          uint32_t ent = 0;
+          if (act) {
+            ent = list[wave][t0 + ln];
+            const PayT q = pay[ent >> 7];
+            const Shift<Q> sh = shifts[ent & 127];
+            jt = pay_tag(q);
+            jx = q.x + sh.x;
+            jy = q.y + sh.y;
+            jz = q.z + sh.z;
+          }
+          const int32_t jidx = tag_index(jt);
+          const int jtype = tag_type(jt);
+          // in-cell candidates (list positions [0, hn)) pair only with homes at lower positions
+          const bool own_cell = c0 + t0 < hn;
+          const int jpos = (int)(ent >> 7);
+          P cx = (P)0, cy = (P)0, cz = (P)0;   // force on the candidate
+#pragma unroll
+          for (int k = 0; k < KMAX; ++k) {
+            if (k < kc) {
+              bool keep = act && (uint32_t)(jidx - lo[k]) > span[k];
+              if (own_cell) keep = keep && ((int)(ent & 127) != ctr || jpos > hs + g0 + k);
+              const int tt = ff.uniform_lj ? 0 : hti[k] * 2 + jtype;
+              if constexpr (FP64) {
+                const double dx = hx[k] - jx, dy = hy[k] - jy, dz = hz[k] - jz;
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                if (keep && r2 < ff.rc2) {
+                  const double r2i = 1.0 / r2;
+                  const double r6 = r2i * r2i * r2i;
+                  const double g = r6 * (pick(cd.f12, tt) * r6 - pick(cd.f6, tt));
+                  const double ffs = g * r2i;
+                  ax[k] += ffs * dx;
+                  ay[k] += ffs * dy;
+                  az[k] += ffs * dz;
+                  cx -= ffs * dx;
+                  cy -= ffs * dy;
+                  cz -= ffs * dz;
+                  if (ENERGY) {
+                    const double en = r6 * (pick(cd.e12, tt) * r6 - pick(cd.e6, tt));
+                    e += en;
+                    es += en - pick(cd.ecut, tt);
+                    w += g;
+                  }
+                }
+              } else {
+                const float dx = (float)(hx[k] - jx), dy = (float)(hy[k] - jy), dz = (float)(hz[k] - jz);
+                const float r2s = r2_fix(dx, dy, dz);
+                bool hit = keep && r2s < bd.hi;
+                if (hit && r2s >= bd.lo) {
+                  // rare: FP32 cannot tell the side of the cutoff; decide from the FP64 positions
+                  double d[3], r2;
+                  hit = inside_cutoff_f64(v.pos, N, B, hidx[k], jidx, ff.rc2, d, r2);
+                }
+                if (hit) {
+                  const float r2 = r2s * kInvFix2F;
+                  const float r2i = rcp_f(r2);
+                  const float r6 = r2i * r2i * r2i;
+                  const float g = r6 * (pick(cf.f12, tt) * r6 - pick(cf.f6, tt));
+                  const float ffs = g * r2i;
+                  ax[k] += ffs * dx;
+                  ay[k] += ffs * dy;
+                  az[k] += ffs * dz;
+                  cx -= ffs * dx;
+                  cy -= ffs * dy;
+                  cz -= ffs * dz;
+                  if (ENERGY) {
+                    const float en = r6 * (pick(cf.e12, tt) * r6 - pick(cf.e6, tt));
+                    e += (double)en;
+                    es += (double)en - (double)pick(cf.ecut, tt);
+                    w += (double)g;
+                  }
+                }
+              }
+            }
+          }
+          if (act && (cx != (P)0 || cy != (P)0 || cz != (P)0)) {
+            deposit(acc + jidx, (double)cx * scale);
+            deposit(acc + N + jidx, (double)cy * scale);
+            deposit(acc + 2 * N + jidx, (double)cz * scale);
+          }
+        }
+      }
+      P sx, sy, sz;
+      sum_homes<P, KMAX>(ln, ax, ay, az, sx, sy, sz);
+      const int hk = ln >> (6 - LV);
+      if ((ln & ((64 >> LV) - 1)) == 0 && hk < kc) {
+        const int32_t i = tag_index(pay_tag(pay[hs + g0 + hk]));
+        deposit(acc + i, (double)sx * scale);
+        deposit(acc + N + i, (double)sy * scale);
+        deposit(acc + 2 * N + i, (double)sz * scale);
+      }
+    }
+  }
+  // each pair counted once: the block sums halve, so pass twice the pair sums
+  if (ENERGY) block_energy<kTileWaves>(2.0 * e, 2.0 * es, 2.0 * w, red, v.part_lj + (int64_t)blk * 3);
+}
+
+// Accumulators -> force array (FP32 or FP64), and back to zero for the next evaluation.
+template <typename P>
+__global__ __launch_bounds__(256) void k_half_finish(Views v) {
+  const int64_t n3 = 3 * v.N;
+  P* f = static_cast<P*>(v.f_lj);
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n3; e += (int64_t)gridDim.x * 256) {
+    const long long a = (long long)v.f_acc[e];
+    f[e] = (P)((double)a * (1.0 / kHalfFix));
+    v.f_acc[e] = 0ull;
+  }
+}
+
 // ---------------------------------------------------------------------------------
 // Neighbour-list mode (Sections 3.1-3.2: the paper's list, rebuilt every few steps).
 //
@@ -1260,7 +1534,7 @@ void launch_tile(const Views& v, const FFDev& ff, const LjPair<float>& cf, const
 }  // namespace
 
 int64_t lj_blocks_for_box(int kernel, int64_t n_atoms, int64_t n_cells) {
-  if (kernel == 2 || kernel == 3 || kernel == 5) return (n_cells + kTileWaves - 1) / kTileWaves;
+  if (kernel == 2 || kernel == 3 || kernel == 5 || kernel == 6) return (n_cells + kTileWaves - 1) / kTileWaves;
   if (kernel == 4) return (n_atoms + kLjNlBlock - 1) / kLjNlBlock;
   return (n_atoms + kLjAtomBlock - 1) / kLjAtomBlock;
 }
@@ -1312,6 +1586,20 @@ void launch_lj_nl(const Views& v, const FFDev& ff, bool fp32, int kernel, bool e
 void launch_lj(const Views& v, const FFDev& ff, bool fp32, int kernel, bool energy, hipStream_t s) {
   const LjPair<float> cf = make_pair<float>(ff);
   const LjPair<double> cd = make_pair<double>(ff);
+  if (kernel == 6) {
+    dim3 g((v.n_lj_blocks + kXcds - 1) / kXcds * kXcds), b(64 * kTileWaves);
+    if (fp32) {
+      if (energy) hipLaunchKernelGGL((k_lj_half<false, true>), g, b, 0, s, v, ff, cf, cd);
+      else hipLaunchKernelGGL((k_lj_half<false, false>), g, b, 0, s, v, ff, cf, cd);
+    } else {
+      if (energy) hipLaunchKernelGGL((k_lj_half<true, true>), g, b, 0, s, v, ff, cf, cd);
+      else hipLaunchKernelGGL((k_lj_half<true, false>), g, b, 0, s, v, ff, cf, cd);
+    }
+    const int fg = (int)std::min<int64_t>((3 * v.N + 255) / 256, 4096);
+    if (fp32) hipLaunchKernelGGL(k_half_finish<float>, dim3(fg), dim3(256), 0, s, v);
+    else hipLaunchKernelGGL(k_half_finish<double>, dim3(fg), dim3(256), 0, s, v);
+    return;
+  }
   if (kernel == 2 || kernel == 3) {
     const bool bl = kernel == 3 && fp32;
     if (fp32) {

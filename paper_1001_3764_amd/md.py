@@ -20,6 +20,7 @@ MD_OK, MD_ERR_ARG, MD_ERR_BOX_TOO_SMALL, MD_ERR_NONFINITE = 0, -1, -2, -3
 MD_ERR_WORKSPACE, MD_ERR_HIP, MD_ERR_STATE, MD_ERR_NLIST = -4, -6, -7, -8
 MD_PREC_FP64, MD_PREC_MIXED = 0, 1
 MD_LJ_AUTO, MD_LJ_ATOM, MD_LJ_CELLTILE, MD_LJ_CELLTILE_NB, MD_LJ_NLIST, MD_LJ_NLIST_TILE = 0, 1, 2, 3, 4, 5
+MD_LJ_HALFSHELL = 6
 MD_INT_VERLET_BERENDSEN, MD_INT_LEAPFROG_NH = 0, 1
 
 _D, _I32, _I64, _P = ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p

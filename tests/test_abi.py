@@ -86,6 +86,12 @@ def test_workspace_bytes_and_validation(md, ff):
     # neighbour-list mode needs the list arrays
     _, nnl = workspace(md, ff, config(md, cell_div=1, lj_kernel=0, nl_skin=1.0, nl_every=10))
     assert nnl > n
+    # the half shell needs its int64 accumulators (24 B per atom); cell path only, R <= 2
+    st_h, nh = workspace(md, ff, config(md, lj_kernel=md.MD_LJ_HALFSHELL))
+    _, ntile = workspace(md, ff, config(md, lj_kernel=md.MD_LJ_CELLTILE))
+    assert st_h == md.MD_OK and nh >= ntile + 24 * 3000
+    assert workspace(md, ff, config(md, lj_kernel=md.MD_LJ_HALFSHELL, nl_skin=1.0, nl_every=10))[0] == md.MD_ERR_ARG
+    assert workspace(md, ff, config(md, lj_kernel=md.MD_LJ_HALFSHELL, cell_div=3))[0] != md.MD_OK
     # both integrators and the COM removal are valid
     for integ in (md.MD_INT_VERLET_BERENDSEN, md.MD_INT_LEAPFROG_NH):
         for com in (False, True):
@@ -97,6 +103,7 @@ def test_workspace_bytes_and_validation(md, ff):
         dict(chain_len=3, n_chains=(1000,)),
         dict(cell_div=4),
         dict(lj_kernel=4),
+        dict(lj_kernel=7),
         dict(nl_skin=-0.5),
         dict(nl_skin=1.0, nl_every=0),
         dict(T0=(float("nan"),)),

@@ -62,7 +62,7 @@ def test_wrap_and_bins_bit_exact_from_outside_the_box(ff, melt):
     s.close()
 
 
-@pytest.mark.parametrize("kernel", [1, 2, 3])
+@pytest.mark.parametrize("kernel", [1, 2, 3, 6])
 @pytest.mark.parametrize("precision,tol", [("fp64", TOL_FP64), ("mixed", TOL_MIXED)])
 @pytest.mark.parametrize("R", [1, 2])
 def test_forces_and_energies(ff, melt, precision, tol, R, kernel):
@@ -93,7 +93,7 @@ def test_forces_and_energies(ff, melt, precision, tol, R, kernel):
     s.close()
 
 
-@pytest.mark.parametrize("kernel", [1, 2])
+@pytest.mark.parametrize("kernel", [1, 2, 6])
 @pytest.mark.parametrize("precision,xtol", [("fp64", 1e-9), ("mixed", 1e-4)])
 def test_trajectory_100_steps(ff, melt, precision, xtol, kernel):
     """The 3,000-atom melt, NVE, 100 steps of 1 fs: positions against the oracle."""
@@ -164,7 +164,7 @@ def test_general_types_and_dihedral_phase(ff, melt):
     fo_lj, eo = O.lj_cells(ffg, melt.pos, melt.types, melt.box, 300)
     fo_b, eb = O.bonded(ffg, melt.pos, melt.box, 300)
     for precision, tol in (("fp64", TOL_FP64), ("mixed", TOL_MIXED)):
-        for kernel in (1, 2):
+        for kernel in (1, 2, 6):
             s = make_system(melt, ffg, precision, 1, lj_kernel=kernel)
             f = s.forces()
             flj = s.forces(lj_only=True)
@@ -176,7 +176,7 @@ def test_general_types_and_dihedral_phase(ff, melt):
 
 
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
-@pytest.mark.parametrize("R,kernel", [(1, 1), (1, 2), (2, 2), (2, 3)])
+@pytest.mark.parametrize("R,kernel", [(1, 1), (1, 2), (2, 2), (2, 3), (1, 6), (2, 6)])
 def test_pairs_at_the_cutoff(ff, precision, R, kernel):
     """Two straight 8-atom chains side by side, atom k of one facing atom k of the other at
     r = rc (1 + delta_k), delta_k from -4e-7 to +4e-7: inside the FP32 uncertainty of r^2.
@@ -210,7 +210,7 @@ def test_pairs_at_the_cutoff(ff, precision, R, kernel):
 
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
 @pytest.mark.parametrize("R,kernel,nl", [(1, 2, False), (2, 2, False), (2, 3, False), (2, 1, False), (1, 4, True),
-                                         (1, 5, True), (2, 5, True)])
+                                         (1, 5, True), (2, 5, True), (1, 6, False), (2, 6, False)])
 def test_many_pairs_at_the_cutoff(ff, precision, R, kernel, nl):
     """One atom with 100 partners on a sphere of radius rc (1 + delta), |delta| <= 4e-7: more
     band pairs than the cell tile's queue holds (64), spread over more than its 8 recorded
@@ -265,7 +265,7 @@ def _ensemble(n_boxes=3):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("kernel", [1, 2, 3])
+@pytest.mark.parametrize("kernel", [1, 2, 3, 6])
 def test_batched_boxes(ff, precision, kernel):
     """Three boxes of different sizes in one context: bins, forces and a 10-step run of each
     box equal the box run alone (bit for bit) and match the oracle."""
@@ -338,3 +338,31 @@ def test_runs_are_bitwise_reproducible(ff, melt):
         runs.append(s.state())
         s.close()
     assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_half_shell_repeats_bitwise_and_matches_full_shell(ff, melt, precision):
+    """MD_LJ_HALFSHELL evaluates each pair once and adds both forces to int64 fixed-point
+    accumulators.  Integer sums do not depend on the order of the atomics, so its forces repeat
+    bit for bit across evaluations and contexts; they equal the full shell's to rounding."""
+    from paper_1001_3764_amd.md import MD_LJ_HALFSHELL
+    a = make_system(melt, ff, precision, 2, lj_kernel=MD_LJ_HALFSHELL)
+    fa = a.forces(lj_only=True)
+    ea = a.energies()[0]
+    for _ in range(3):   # evaluate again: the accumulators were cleared after the last use
+        a.compute_forces(with_energy=False)
+    fa2 = a.forces(lj_only=True)
+    c = make_system(melt, ff, precision, 2, lj_kernel=MD_LJ_HALFSHELL)
+    fc = c.forces(lj_only=True)
+    assert np.array_equal(fa, fa2) and np.array_equal(fa, fc)
+    b = make_system(melt, ff, precision, 2, lj_kernel=2)
+    fb = b.forces(lj_only=True)
+    eb = b.energies()[0]
+    tol = TOL_FP64 if precision == "fp64" else 2 * TOL_MIXED
+    err = norm_err(fa, fb)
+    print("half shell vs full shell (%s): %.3e" % (precision, err))
+    assert err <= tol
+    assert ea["e_lj"] == pytest.approx(eb["e_lj"], rel=1e-12 if precision == "fp64" else 2e-6)
+    assert ea["virial"] == pytest.approx(eb["virial"], rel=1e-11 if precision == "fp64" else 2e-6)
+    for s in (a, b, c):
+        s.close()
