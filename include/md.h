@@ -79,8 +79,8 @@ typedef enum {
                             any atom of the cell at the build), streamed by the cell-tile kernel
                             against the cell's atoms */
   MD_LJ_HALFSHELL = 6    /* cell path, opt-in (never chosen by the autotuner): each pair evaluated
-                            once (Newton's third law; the paper's Section 4 names the doubled
-                            pair work of its per-atom kernels as an inefficiency), both forces
+                            once (Newton's third law; the paper's Section 4.2 names the doubled
+                            pair work of its per-atom kernels as a cost), both forces
                             added to int64 fixed-point accumulators with device atomics, so the
                             sums are exact and order-independent.  Measured slower than the full
                             shell on this device: the atomics cost more than the second

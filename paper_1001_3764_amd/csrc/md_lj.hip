@@ -940,8 +940,8 @@ __device__ __forceinline__ void sum_homes(int ln, P (&ax)[KMAX], P (&ay)[KMAX], 
 }
 
 // ---------------------------------------------------------------------------------
-// Newton-3 half shell (MD_LJ_HALFSHELL, opt-in; the inefficiency Section 4 names in its
-// thread-per-atom kernels is that every pair is computed twice).  Each pair is evaluated once:
+// Newton-3 half shell (MD_LJ_HALFSHELL, opt-in; Section 4.2 names as a cost of its
+// thread-per-atom kernels that every pair is computed twice).  Each pair is evaluated once:
 // a home cell's wave lists its own atoms and the forward half of its stencil (codes above the
 // centre), and takes an in-cell pair only from the lower of the two sorted positions.  The
 // force on each candidate (the reaction, summed on its lane over the group's homes) and on
