@@ -176,6 +176,8 @@ __device__ inline double uni(double x) {
 template <typename P>
 struct LjPair {
   P f12[4], f6[4], e12[4], e6[4], ecut[4];
+  P f12_fold;               // f12[0] / f6[0] (one type pair: the force factor's inline constant)
+  float band_lo, band_hi;   // the cutoff band of make_band, computed once on the host
 };
 
 template <typename P>
@@ -687,9 +689,9 @@ void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
   if (wact) {
     const int hs = __builtin_amdgcn_readfirstlane(cs[B.cell_off + lc]);
     const int hn = __builtin_amdgcn_readfirstlane(cs[B.cell_off + lc + 1]) - hs;
-    const Band bd = make_band(ff.rc2);
+    const Band bd{cf.band_lo, cf.band_hi};
     // one type pair (mixed): forces are summed divided by f6 (see pair_fix)
-    const float f12_fold = cf.f12[0] / cf.f6[0];
+    const float f12_fold = cf.f12_fold;
     const float fscale = UNI ? kInvFixF * cf.f6[0] : kInvFixF;
     for (int g0 = 0; g0 < hn; g0 += KMAX) {
       const int kc = min(KMAX, hn - g0);
@@ -1513,6 +1515,10 @@ LjPair<P> make_pair(const FFDev& ff) {
     c.e6[t] = (P)ff.e6[t];
     c.ecut[t] = (P)ff.ecut[t];
   }
+  c.f12_fold = c.f12[0] / c.f6[0];
+  // the same expressions as make_band (products only, so no contraction can differ)
+  c.band_lo = (float)(ff.rc2 * kFix * kFix * (1.0 - kBand));
+  c.band_hi = (float)(ff.rc2 * kFix * kFix * (1.0 + kBand));
   return c;
 }
 
