@@ -160,6 +160,28 @@ def test_melt300k_neighbour_lists_sampled_forces(ff, melt300k):
     s.close()
 
 
+def test_melt300k_half_shell_sampled_forces_and_energies(ff, melt300k):
+    """The Newton-3 half shell (opt-in MD_LJ_HALFSHELL) as the benchmark runs it (R = 2, graph):
+    every bonded force, 2,000 sampled LJ forces and the energies against the oracle; 10 steps in,
+    bit-identical to a second context (integer sums do not depend on the order of the atomics)."""
+    from paper_1001_3764_amd.md import MD_LJ_HALFSHELL
+    wl = WORKLOADS["melt300k_mixed"]
+    s = system(ff, [melt300k], wl, cell_div=2, lj_kernel=MD_LJ_HALFSHELL, use_graph=True)
+    check_sampled_forces(ff, s, melt300k, 2000, 43)
+    e = s.energies()[0]
+    _, eo = O.lj_cells(ff, melt300k.pos, melt300k.types, melt300k.box, 300)
+    _, eb = O.bonded(ff, melt300k.pos, melt300k.box, 300)
+    energy_close(e, {**eo, **eb})
+    t = system(ff, [melt300k], wl, cell_div=2, lj_kernel=MD_LJ_HALFSHELL, use_graph=True)
+    s.step(10)
+    t.step(10)
+    ps, vs = s.state()
+    pt, vt = t.state()
+    assert np.array_equal(ps, pt) and np.array_equal(vs, vt)
+    s.close()
+    t.close()
+
+
 def test_melt3M_bins_and_sampled_forces(ff):
     """3,000,000 atoms at 0.85 g/cm^3: bins bit-exact, every bonded force, 2,000 sampled LJ
     forces."""
