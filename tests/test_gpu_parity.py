@@ -366,3 +366,58 @@ def test_half_shell_repeats_bitwise_and_matches_full_shell(ff, melt, precision):
     assert ea["virial"] == pytest.approx(eb["virial"], rel=1e-11 if precision == "fp64" else 2e-6)
     for s in (a, b, c):
         s.close()
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+@pytest.mark.parametrize("kernel", [1, 2, 3, 6])
+def test_pairs_at_the_cutoff_from_the_corners_of_a_home_group(ff, precision, kernel):
+    """Four atoms in one cell (R = 2), at four corners of the box that bounds them, each with 7
+    partners at r = rc (1 + delta), |delta| <= 4e-7, in directions pointing away from that box
+    (well spaced: points of a 100-point Fibonacci sphere in that octant).
+    There a partner's distance to the box equals its distance to the home: the tightest case
+    for the cell tile's bounding-box filter, whose r^2 then equals the pair test's.  The LJ pair
+    set must be the FP64 one, so every LJ force matches the oracle's far below |F(rc)|."""
+    rc = ff["rc"]
+    L = 60.0
+    edge = L / np.floor(L * 2 / rc)
+    lo, hi = 5 * edge + 0.3, 6 * edge - 0.3            # inside cell (5, 5, 5)
+    homes = np.array([[lo, lo, lo], [hi, lo, lo], [lo, hi, lo], [lo, lo, hi]]).T
+    outward = np.array([[-1, -1, -1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], float).T
+    rng = np.random.default_rng(5)
+    m = 100
+    g = (1 + 5 ** 0.5) / 2
+    t = np.arange(m) + 0.5
+    sph = np.stack([np.cos(2 * np.pi * t / g) * np.sqrt(1 - (1 - 2 * t / m) ** 2),
+                    np.sin(2 * np.pi * t / g) * np.sqrt(1 - (1 - 2 * t / m) ** 2), 1 - 2 * t / m])
+    partners, deltas = [], []
+    for k in range(4):
+        inside = np.all(sph * outward[:, k:k + 1] >= 0.15, axis=0)
+        u = sph[:, inside][:, :7]
+        assert u.shape[1] == 7
+        d = rng.uniform(1e-9, 4e-7, 7) * np.where(np.arange(7) % 2 == 0, 1.0, -1.0)
+        partners.append(homes[:, k:k + 1] + rc * (1 + d) * u)
+        deltas.append(d)
+    # home chains: the home and three atoms far from everything else
+    chains = []
+    for k in range(4):
+        far = np.array([[4.0 + 1.6 * j, 4.0 + 3.0 * k, 4.0] for j in range(3)]).T
+        chains.append(np.concatenate([homes[:, k:k + 1], far], axis=1))
+    pos = np.concatenate(chains + partners, axis=1)
+    box = np.array([L, L, L])
+    types = np.zeros(pos.shape[1], dtype=np.uint8)
+    # the oracle's own decisions on the designed pairs: inside iff delta < 0
+    for k in range(4):
+        dd = partners[k] - homes[:, k:k + 1]
+        assert np.array_equal(np.sum(dd * dd, axis=0) < rc * rc, deltas[k] < 0)
+    fo, _ = O.lj_brute(ff, pos, types, box, 4)
+    from paper_1001_3764_amd.md import MDSystem
+    print("corner cutoff pairs: precision=%s kernel=%d" % (precision, kernel), flush=True)
+    s = MDSystem(ff, [pos.shape[1] // 4], box[None, :], [0.0], pos, np.zeros_like(pos), types, chain_len=4,
+                 precision=precision, cell_div=2, lj_kernel=kernel)
+    M, _, _ = s.grid(0)
+    assert np.all(M == 11)
+    flj = s.forces(lj_only=True)
+    s.close()
+    s6 = ff["sigma"][0] ** 6
+    f_rc = 4 * ff["epsilon"][0] * (12 * s6 * s6 / rc ** 13 - 6 * s6 / rc ** 7)
+    assert np.max(np.abs(flj - fo)) < 0.02 * abs(f_rc)
