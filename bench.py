@@ -68,9 +68,15 @@ LJ_SOURCE = os.path.join(ROOT, "paper_1001_3764_amd", "csrc", "md_lj.hip")
 
 
 def lj_source_hash():
+    """SHA-256 of the LJ kernels' source with comments and blank lines left out, so that the
+    counter record follows the code, not its commentary."""
     import hashlib
-    with open(LJ_SOURCE, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()
+    import re
+    with open(LJ_SOURCE) as fh:
+        text = fh.read()
+    lines = [re.sub(r"//.*$", "", line).rstrip() for line in text.splitlines()]
+    code = "\n".join(line for line in lines if line.strip())
+    return hashlib.sha256(code.encode()).hexdigest()
 
 
 def measured_traffic(kernel_name):

@@ -12,12 +12,17 @@
 // in the home cell's frame.  Mixed precision keeps these as int32 fixed point
 // (2^-25 A), so x_i - x_j is an exact integer rounded once to FP32; FP64 uses doubles.
 //
-// Two kernels:
-//   k_lj_atom  one lane per home atom walking the stencil cells (the paper's shape);
-//   k_lj_tile  one wavefront per home cell: the cell's atoms are wave-uniform (KMAX
-//              at a time) and candidate atoms stream across the lanes, two stencil
-//              rows at a time (one per 32-lane half), so lanes stay busy whatever
-//              the cell occupancy.
+// Kernels:
+//   k_lj_atom        one lane per home atom walking the stencil cells (the paper's shape);
+//   k_lj_tile        one wavefront per home cell: the cell's atoms are wave-uniform (KMAX
+//                    at a time) and the stencil's atoms, listed flat in LDS and filtered
+//                    by the box bounding the homes, stream across the lanes 64 at a time;
+//                    with LIST the candidates are the cell's neighbour list instead;
+//   k_lj_half        the same layout over half the stencil, each pair once, both forces
+//                    added to int64 fixed-point accumulators (opt-in);
+//   k_nl_build,      neighbour-list builds (Sections 3.1-3.2), per atom and per cell, and
+//   k_nl_build_tile, the per-atom list walk.
+//   k_lj_nl
 #include <type_traits>
 
 #include "md_internal.h"
