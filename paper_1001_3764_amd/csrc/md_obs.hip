@@ -3,8 +3,10 @@
 // gauche fractions (Figs. 9, 15), and per-chain radius of gyration and end-to-end vector
 // (Figs. 8, 12).
 //
-//   k_obs_pairs      one lane per atom of the sorted order: the cells of the current grid
-//                    around its cell; every unordered non-excluded pair once (j > i); the
+//   k_obs_pairs      one lane per atom of the sorted order: its own cell (the atoms after it
+//                    in the sorted order) and the forward half of the current grid's stencil
+//                    (with at least 2R + 1 cells per dimension no pair of cells is reached from
+//                    both sides), so every unordered non-excluded pair is counted once; the
 //                    bin is decided in FP64 on r^2 against squared edges, so the counts are
 //                    exact integers; a block histogram in LDS (integer atomics: the counts
 //                    do not depend on their order), one row of block partials per block
@@ -50,7 +52,8 @@ __global__ __launch_bounds__(kAtomBlock) void k_obs_pairs(Views v, int b, int ch
     const Cell3 k3 = cell_coords(lc, B);
     const double xi = v.pos[i], yi = v.pos[N + i], zi = v.pos[2 * N + i];
     const int32_t ci = i / chain_len;
-    for (int code = 0; code < W * W * W; ++code) {
+    const int ctr = (W * W * W - 1) / 2;   // the cell itself; codes above it are the forward half
+    for (int code = ctr; code < W * W * W; ++code) {
       const Cell3 o = stencil_offset(code, R);
       int nx = k3.x + o.x, ny = k3.y + o.y, nz = k3.z + o.z;
       nx += nx < 0 ? M0 : 0;
@@ -61,10 +64,9 @@ __global__ __launch_bounds__(kAtomBlock) void k_obs_pairs(Views v, int b, int ch
       nz -= nz >= M2 ? M2 : 0;
       const int c = B.cell_off + nx + M0 * (ny + M1 * nz);
       const int32_t e = v.cell_start[c + 1];
-      for (int32_t t = v.cell_start[c]; t < e; ++t) {
+      for (int32_t t = code == ctr ? (int32_t)s + 1 : v.cell_start[c]; t < e; ++t) {
         const int32_t j = v.cell_atoms[t];
-        if (j <= i) continue;
-        if (j / chain_len == ci && j - i <= excl) continue;
+        if (j / chain_len == ci && abs(j - i) <= excl) continue;
         const double dx = mi_rn(__dadd_rn(xi, -v.pos[j]), B.L[0], B.invL[0]);
         const double dy = mi_rn(__dadd_rn(yi, -v.pos[N + j]), B.L[1], B.invL[1]);
         const double dz = mi_rn(__dadd_rn(zi, -v.pos[2 * N + j]), B.L[2], B.invL[2]);
