@@ -470,7 +470,12 @@ md_status capture_graphs(md_ctx* c) {
   return MD_OK;
 }
 
-// Times rebuild + forces for each candidate and keeps the fastest.
+// A candidate replaces the best so far only when it is faster by this fraction: candidates
+// within timing noise of each other (the cell tile with and without branching) then resolve
+// to the same choice on every run.
+constexpr float kTuneMargin = 0.03f;
+
+// Times rebuild + forces for each candidate and keeps the fastest (see kTuneMargin).
 md_status autotune(md_ctx* c, const md_config* cfg, int* bestR, int* bestK) {
   std::vector<int> Rs, Ks;
   if (cfg->cell_div) Rs.push_back(cfg->cell_div);
@@ -517,7 +522,7 @@ md_status autotune(md_ctx* c, const md_config* cfg, int* bestR, int* bestK) {
       if ((st = hip_check(c, hipEventSynchronize(e1), "autotune sync"))) break;
       float ms = 0;
       (void)hipEventElapsedTime(&ms, e0, e1);
-      if (ms < best) {
+      if (ms < best * (1.0f - kTuneMargin)) {
         best = ms;
         *bestR = R;
         *bestK = K;
