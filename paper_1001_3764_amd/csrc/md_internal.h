@@ -223,7 +223,7 @@ void launch_nl_build(const Views& v, const FFDev& ff, bool fp32, int kernel, hip
 void launch_lj_nl(const Views& v, const FFDev& ff, bool fp32, int kernel, bool energy, bool build_step,
                   hipStream_t s);
 constexpr int kLjNlBlock = 256;   // threads per block of the list force kernel (box-aligned)
-constexpr int kTileWaves = 4;     // home cells per block of the cell-tile kernel
+constexpr int kTileWaves = 1;     // home cells (wavefronts) per block of the cell-tile kernels
 constexpr int kXcds = 8;          // accelerator complex dies of an MI355X (one L2 each)
 constexpr int kTileMaxR = 2;      // stencil radii the cell-tile kernel supports
 

@@ -676,8 +676,7 @@ void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
   // stencil offsets in the payload's units (the same for every wave of the block)
   {
     const int R = v.R, W = 2 * R + 1;
-    const int code = (int)threadIdx.x;
-    if (code < W * W * W) {
+    for (int code = (int)threadIdx.x; code < W * W * W; code += (int)blockDim.x) {
       const Cell3 o = stencil_offset(code, R);
       const int ox = o.x, oy = o.y, oz = o.z;
       if constexpr (FP64)
@@ -1015,8 +1014,7 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_lj_half(Views v, FFDev ff, 
   const PayT* __restrict__ pay = static_cast<const PayT*>(v.payload);
   const int R = v.R, W = 2 * R + 1, ctr = (W * W * W - 1) / 2;
   {
-    const int code = (int)threadIdx.x;
-    if (code < W * W * W) {
+    for (int code = (int)threadIdx.x; code < W * W * W; code += (int)blockDim.x) {
       const Cell3 o = stencil_offset(code, R);
       if constexpr (FP64)
         shifts[code] = Shift<Q>{o.x * B.edge[0], o.y * B.edge[1], o.z * B.edge[2]};
@@ -1207,8 +1205,7 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_nl_build(Views v, FFDev ff)
   const PayT* __restrict__ pay = static_cast<const PayT*>(v.payload);
   {
     const int R = v.R, W = 2 * R + 1;
-    const int code = (int)threadIdx.x;
-    if (code < W * W * W) {
+    for (int code = (int)threadIdx.x; code < W * W * W; code += (int)blockDim.x) {
       const Cell3 o = stencil_offset(code, R);
       const int ox = o.x, oy = o.y, oz = o.z;
       if constexpr (FP64)
@@ -1327,8 +1324,7 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_nl_build_tile(Views v, FFDe
   const PayT* __restrict__ pay = static_cast<const PayT*>(v.payload);
   {
     const int R = v.R, W = 2 * R + 1;
-    const int code = (int)threadIdx.x;
-    if (code < W * W * W) {
+    for (int code = (int)threadIdx.x; code < W * W * W; code += (int)blockDim.x) {
       const Cell3 o = stencil_offset(code, R);
       const int ox = o.x, oy = o.y, oz = o.z;
       if constexpr (FP64)
@@ -1423,8 +1419,7 @@ __global__ __launch_bounds__(kLjNlBlock) void k_lj_nl(Views v, FFDev ff, LjPair<
   const int local = ((int)blockIdx.x - B.lj_blk_off) * kLjNlBlock + (int)threadIdx.x;
   {
     const int R = v.R, W = 2 * R + 1;
-    const int code = (int)threadIdx.x;
-    if (code < W * W * W) {
+    for (int code = (int)threadIdx.x; code < W * W * W; code += (int)blockDim.x) {
       const Cell3 o = stencil_offset(code, R);
       const int ox = o.x, oy = o.y, oz = o.z;
       if constexpr (FP64)
