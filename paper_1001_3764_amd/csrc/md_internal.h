@@ -14,6 +14,7 @@ constexpr int kLjAtomBlock = 128; // threads per block of the lane-per-atom LJ k
 constexpr int kScanItems = 4;     // cells per thread in the scan
 constexpr int kScanBlock = 1024;
 constexpr int kScanTile = kScanItems * kScanBlock;
+constexpr int kScanOnePass = 16;  // at most this many tiles: the one-launch scan
 constexpr int kHalo = 3;          // a dihedral reaches 3 atoms beyond its first atom
 
 // acceleration of 1 kcal/mol/A on 1 g/mol, in A/fs^2; gas constant in kcal/mol/K

@@ -6,9 +6,11 @@
 //   k_bin_count     wrap, cell index, slot = atomic count (one atomic per distinct
 //                   cell per wavefront, all issued at once, lanes ranked with
 //                   ballot/popcount)
-//   k_scan_tiles    the total count of each tile of cells
+//   k_scan_tiles    the total count of each tile of cells (grids of more than
+//                   kScanOnePass tiles)
 //   k_scan          cell_start = exclusive prefix sum of the counts (each tile's offset is
-//                   the sum of the totals of the tiles before it)
+//                   the sum of the totals of the tiles before it, or on small grids of
+//                   their counts)
 //   k_scatter       unordered lists: tmp[cell_start[c] + slot] = atom
 //   k_rank_payload  rank inside the cell = number of smaller atom indices in it;
 //                   writes the ordered list and the cell-centre-relative payload
@@ -91,7 +93,7 @@ template <typename F, bool KICK>
 __global__ __launch_bounds__(kAtomBlock) void k_bin_count(Views v, const F* __restrict__ f, double dt,
                                                         double kdt, FFDev ff) {
   const int b = v.blk_box[blockIdx.x];
-  const BoxDev& B = v.boxes[b];
+  const BoxDev B = v.boxes[b];   // read at entry, before any store: scalar loads
   const int local = ((int)blockIdx.x - B.blk_off) * kAtomBlock + (int)threadIdx.x;
   const bool active = local < B.n_atoms;
   const int64_t N = v.N;
@@ -179,13 +181,25 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_tiles(const int32_t* __rest
 
 // Tile b's offset is the sum of the tile totals tiles[0..b) (each block sums them itself: no
 // separate pass over the tile totals), then the tile's own counts are scanned (k_scatter
-// clears them for the next binning).
+// clears them for the next binning).  ONE (grids of at most kScanOnePass tiles): no tile
+// totals; block b sums the counts of tiles 0..b-1 itself (all full tiles: each thread reads
+// its four counts of each, the reads in flight together), one launch instead of two.
+template <bool ONE>
 __global__ __launch_bounds__(kScanBlock) void k_scan(int32_t* __restrict__ cnt, int64_t C,
                                                     const int32_t* __restrict__ tiles,
                                                     int32_t* __restrict__ cell_start) {
   __shared__ int sh[33];
   int pre = 0;
-  for (int t = (int)threadIdx.x; t < (int)blockIdx.x; t += kScanBlock) pre += tiles[t];
+  if constexpr (ONE) {
+    const int4* __restrict__ c4 = reinterpret_cast<const int4*>(cnt);
+#pragma unroll 4
+    for (int t = 0; t < (int)blockIdx.x; ++t) {
+      const int4 q = c4[(int64_t)t * (kScanTile / 4) + threadIdx.x];
+      pre += (q.x + q.y) + (q.z + q.w);
+    }
+  } else {
+    for (int t = (int)threadIdx.x; t < (int)blockIdx.x; t += kScanBlock) pre += tiles[t];
+  }
   int offset;
   block_exclusive_scan(pre, sh, &offset);
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
@@ -205,15 +219,20 @@ __global__ __launch_bounds__(kScanBlock) void k_scan(int32_t* __restrict__ cnt, 
 }
 
 __global__ __launch_bounds__(kAtomBlock) void k_scatter(Views v) {
-  // the scan has read the counts: clear them for the next binning
-  for (int64_t c = (int64_t)blockIdx.x * kAtomBlock + threadIdx.x; c < v.C; c += (int64_t)gridDim.x * kAtomBlock)
-    v.cnt[c] = 0;
   const int b = v.blk_box[blockIdx.x];
-  const BoxDev& B = v.boxes[b];
+  const BoxDev B = v.boxes[b];   // read at entry, before any store: scalar loads
   const int local = ((int)blockIdx.x - B.blk_off) * kAtomBlock + (int)threadIdx.x;
-  if (local >= B.n_atoms) return;
+  const bool active = local < B.n_atoms;
   const int64_t i = (int64_t)B.atom_off + local;
-  v.tmp[v.cell_start[v.cell[i]] + v.slot[i]] = (int32_t)i;
+  int32_t c = 0, sl = 0;
+  if (active) {
+    c = v.cell[i];
+    sl = v.slot[i];
+  }
+  // the scan has read the counts: clear them for the next binning
+  for (int64_t k = (int64_t)blockIdx.x * kAtomBlock + threadIdx.x; k < v.C; k += (int64_t)gridDim.x * kAtomBlock)
+    v.cnt[k] = 0;
+  if (active) v.tmp[v.cell_start[c] + sl] = (int32_t)i;
 }
 
 template <typename PayT>
@@ -235,31 +254,43 @@ __device__ inline void store_payload<Pay64>(Pay64* p, int64_t dst, double rx, do
   p[dst] = q;
 }
 
+constexpr int kRankBatch = 4;   // list entries read together by the rank walk
+
 template <typename PayT>
 __global__ __launch_bounds__(kAtomBlock) void k_rank_payload(Views v) {
   const int b = v.blk_box[blockIdx.x];
-  const BoxDev& B = v.boxes[b];
+  const BoxDev B = v.boxes[b];   // read at entry, before any store: scalar loads
   const int local = ((int)blockIdx.x - B.blk_off) * kAtomBlock + (int)threadIdx.x;
   if (local >= B.n_atoms) return;
   const int64_t N = v.N;
   const int32_t i = B.atom_off + local;
+  // the loads that depend on i alone go first, so they are in flight during the rank walk
+  const double x = v.pos[i], y = v.pos[N + i], z = v.pos[2 * N + i];
+  const int32_t ty = v.type[i];
   const int32_t c = v.cell[i];
   const int32_t s0 = v.cell_start[c];
   const int32_t n = v.cell_start[c + 1] - s0;
+  // the unordered list in batches of kRankBatch entries whose loads are in flight together;
+  // entries past the end re-read the last one (atom i is in the cell, so n >= 1) and count 0
   int rank = 0;
-  for (int k = 0; k < n; ++k) rank += v.tmp[s0 + k] < i;
+  for (int k0 = 0; k0 < n; k0 += kRankBatch) {
+    int32_t t[kRankBatch];
+#pragma unroll
+    for (int u = 0; u < kRankBatch; ++u) t[u] = v.tmp[s0 + min(k0 + u, n - 1)];
+#pragma unroll
+    for (int u = 0; u < kRankBatch; ++u) rank += (k0 + u < n && t[u] < i) ? 1 : 0;
+  }
   if (rank >= n) rank = n - 1;   // only reachable if the lists were inconsistent
   const int32_t dst = s0 + rank;
   v.cell_atoms[dst] = i;
   v.scell[dst] = c;
-  const double x = v.pos[i], y = v.pos[N + i], z = v.pos[2 * N + i];
   const int kx = cell_coord(x, B.cinv[0], B.M[0]);
   const int ky = cell_coord(y, B.cinv[1], B.M[1]);
   const int kz = cell_coord(z, B.cinv[2], B.M[2]);
   const double rx = x - ((double)kx + 0.5) * B.edge[0];
   const double ry = y - ((double)ky + 0.5) * B.edge[1];
   const double rz = z - ((double)kz + 0.5) * B.edge[2];
-  const int32_t tag = (i << 4) | ((int32_t)(v.type[i] & 1) << 3) | (kx & 7);
+  const int32_t tag = (i << 4) | ((ty & 1) << 3) | (kx & 7);
   store_payload<PayT>(static_cast<PayT*>(v.payload), dst, rx, ry, rz, tag);
   if (v.nl_cap) {   // neighbour-list mode: where the list build saw the atom
     v.slot_of[i] = dst;
@@ -299,7 +330,7 @@ template <typename F, typename PayT>
 __global__ __launch_bounds__(kAtomBlock) void k_nl_integrate(Views v, const F* __restrict__ f, double dt,
                                                           double kdt, FFDev ff) {
   const int b = v.blk_box[blockIdx.x];
-  const BoxDev& B = v.boxes[b];
+  const BoxDev B = v.boxes[b];   // read at entry, before any store: scalar loads
   const int local = ((int)blockIdx.x - B.blk_off) * kAtomBlock + (int)threadIdx.x;
   if (local >= B.n_atoms) return;
   const int64_t N = v.N;
@@ -394,7 +425,7 @@ __global__ __launch_bounds__(kAtomBlock) void k_bonded(Views v, FFDev ff, double
   __shared__ dd red[kAtomBlock / 64][NP];
 
   const int b = v.blk_box[blockIdx.x];
-  const BoxDev& B = v.boxes[b];
+  const BoxDev B = v.boxes[b];   // read at entry, before any store: scalar loads
   const int64_t N = v.N;
   const int32_t g0 = B.atom_off + ((int)blockIdx.x - B.blk_off) * kAtomBlock;
   const int32_t box_end = B.atom_off + B.n_atoms;
@@ -599,7 +630,7 @@ __global__ __launch_bounds__(256) void k_reduce(Views v, int update, StepOpts o)
   constexpr int iP = 1, iE = COM ? 4 : 1, NV = iE + (ENERGY ? 7 : 0);
   __shared__ dd sh[4][NV];
   const int b = blockIdx.x;
-  const BoxDev& B = v.boxes[b];
+  const BoxDev B = v.boxes[b];   // read at entry, before any store: scalar loads
   const int first = B.blk_off;
   const int count = (B.n_atoms + kAtomBlock - 1) / kAtomBlock;
   dd q[NV];
@@ -671,7 +702,7 @@ __global__ __launch_bounds__(256) void k_reduce(Views v, int update, StepOpts o)
 // Applies the pending Berendsen factor (velocity Verlet) and COM velocity to v.
 __global__ __launch_bounds__(kAtomBlock) void k_finalize(Views v, int lf) {
   const int b = v.blk_box[blockIdx.x];
-  const BoxDev& B = v.boxes[b];
+  const BoxDev B = v.boxes[b];   // read at entry, before any store: scalar loads
   const int local = ((int)blockIdx.x - B.blk_off) * kAtomBlock + (int)threadIdx.x;
   if (local >= B.n_atoms) return;
   const int64_t N = v.N;
@@ -736,8 +767,12 @@ static int scan_tiles(const Views& v) { return (int)((v.C + kScanTile - 1) / kSc
 
 void launch_scan(const Views& v, hipStream_t s) {
   const int n = scan_tiles(v);
+  if (n <= kScanOnePass) {
+    hipLaunchKernelGGL(k_scan<true>, dim3(n), dim3(kScanBlock), 0, s, v.cnt, v.C, v.scan_tiles, v.cell_start);
+    return;
+  }
   hipLaunchKernelGGL(k_scan_tiles, dim3(n), dim3(kScanBlock), 0, s, v.cnt, v.C, v.scan_tiles);
-  hipLaunchKernelGGL(k_scan, dim3(n), dim3(kScanBlock), 0, s, v.cnt, v.C, v.scan_tiles, v.cell_start);
+  hipLaunchKernelGGL(k_scan<false>, dim3(n), dim3(kScanBlock), 0, s, v.cnt, v.C, v.scan_tiles, v.cell_start);
 }
 
 void launch_scatter(const Views& v, hipStream_t s) {

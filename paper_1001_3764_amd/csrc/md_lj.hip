@@ -242,6 +242,16 @@ __device__ __forceinline__ void remove_band_pair(const double (&d)[3], double r2
   }
 }
 
+// x clamped to [lo, hi] (lo <= hi), for the bounding-box filter.  Fixed point: the median
+// of the three in one instruction (the compiler cannot prove lo <= hi, and a max and a min
+// are two); FP64: a max and a min.
+__device__ __forceinline__ int clamp_box(int x, int lo, int hi) {
+  int r;
+  asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(lo), "v"(hi));
+  return r;
+}
+__device__ __forceinline__ double clamp_box(double x, double lo, double hi) { return min(max(x, lo), hi); }
+
 // FP32 r^2 of an exact fixed-point difference (units of 2^-50 A^2).  Written with explicit
 // fused multiply-adds so that every call site rounds identically.
 __device__ __forceinline__ float r2_fix(float dx, float dy, float dz) {
@@ -758,14 +768,14 @@ void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
         const double rc2_keep = ff.rc2 * (1.0 + 1e-12);
         int m = 0;
         // kFilter steps per batch with their loads in flight together (lanes past the end
-        // load entry 0, a valid payload index and stencil code, and are masked out); a
-        // batch reads all its entries before it writes any
+        // re-read the last entry, a valid payload index and stencil code, and are masked
+        // out); a batch reads all its entries before it writes any
         constexpr int kFilter = FP64 ? 2 : kFilterSteps;
         for (int t0 = 0; t0 < total; t0 += 64 * kFilter) {
           uint32_t ent[kFilter];
           Q jx[kFilter], jy[kFilter], jz[kFilter];
 #pragma unroll
-          for (int u = 0; u < kFilter; ++u) ent[u] = t0 + 64 * u + ln < total ? list[wave][t0 + 64 * u + ln] : 0u;
+          for (int u = 0; u < kFilter; ++u) ent[u] = list[wave][min(t0 + 64 * u + ln, total - 1)];
 #pragma unroll
           for (int u = 0; u < kFilter; ++u) {
             const PayT q = pay[ent[u] >> 7];
@@ -776,8 +786,8 @@ void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
           }
 #pragma unroll
           for (int u = 0; u < kFilter; ++u) {
-            const Q dx = jx[u] - min(max(jx[u], lox), hix), dy = jy[u] - min(max(jy[u], loy), hiy),
-                    dz = jz[u] - min(max(jz[u], loz), hiz);
+            const Q dx = jx[u] - clamp_box(jx[u], lox, hix), dy = jy[u] - clamp_box(jy[u], loy, hiy),
+                    dz = jz[u] - clamp_box(jz[u], loz, hiz);
             bool pass;
             if constexpr (FP64)
               pass = dx * dx + dy * dy + dz * dz < rc2_keep;
@@ -802,17 +812,12 @@ void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
         const int cn = min(kListCap, ncand - c0);
         for (int t0 = 0; t0 < cn; t0 += 64) {
           const bool act = t0 + ln < cn;
-          Q jx = (Q)0, jy = (Q)0, jz = (Q)0;
-          int32_t jt = 0;
-          if (act) {
-            const uint32_t ent = list[wave][t0 + ln];
-            const PayT q = pay[ent >> 7];
-            const Shift<Q> sh = shifts[ent & 127];
-            jt = pay_tag(q);
-            jx = q.x + sh.x;
-            jy = q.y + sh.y;
-            jz = q.z + sh.z;
-          }
+          // lanes past the end re-read entry t0, a valid candidate that keep then masks out
+          const uint32_t ent = list[wave][t0 + (act ? ln : 0)];
+          const PayT q = pay[ent >> 7];
+          const Shift<Q> sh = shifts[ent & 127];
+          const int32_t jt = pay_tag(q);
+          const Q jx = q.x + sh.x, jy = q.y + sh.y, jz = q.z + sh.z;
           const int32_t jidx = tag_index(jt);
           const int jtype = tag_type(jt);
 #pragma unroll
