@@ -140,28 +140,29 @@ __global__ __launch_bounds__(kAtomBlock) void k_bin_count(Views v, const F* __re
 }
 
 // ---- exclusive scan of the counts ----
-__device__ int block_exclusive_scan(int val, int* sh, int* total) {
+template <typename T>
+__device__ T block_exclusive_scan(T val, T* sh, T* total) {
   const int ln = lane(), w = (int)threadIdx.x >> 6;
   const int nw = (int)blockDim.x >> 6;
-  int inc = val;
+  T inc = val;
   for (int d = 1; d < 64; d <<= 1) {
-    int t = __shfl_up(inc, d, 64);
+    T t = __shfl_up(inc, d, 64);
     if (ln >= d) inc += t;
   }
   if (ln == 63) sh[w] = inc;
   __syncthreads();
   if (w == 0) {
-    int x = ln < nw ? sh[ln] : 0;
-    int xi = x;
+    T x = ln < nw ? sh[ln] : 0;
+    T xi = x;
     for (int d = 1; d < 64; d <<= 1) {
-      int t = __shfl_up(xi, d, 64);
+      T t = __shfl_up(xi, d, 64);
       if (ln >= d) xi += t;
     }
     if (ln < nw) sh[ln] = xi - x;
     if (ln == nw - 1) sh[32] = xi;
   }
   __syncthreads();
-  const int ex = sh[w] + inc - val;
+  const T ex = sh[w] + inc - val;
   *total = sh[32];
   __syncthreads();
   return ex;
@@ -188,20 +189,7 @@ template <bool ONE>
 __global__ __launch_bounds__(kScanBlock) void k_scan(int32_t* __restrict__ cnt, int64_t C,
                                                     const int32_t* __restrict__ tiles,
                                                     int32_t* __restrict__ cell_start) {
-  __shared__ int sh[33];
-  int pre = 0;
-  if constexpr (ONE) {
-    const int4* __restrict__ c4 = reinterpret_cast<const int4*>(cnt);
-#pragma unroll 4
-    for (int t = 0; t < (int)blockIdx.x; ++t) {
-      const int4 q = c4[(int64_t)t * (kScanTile / 4) + threadIdx.x];
-      pre += (q.x + q.y) + (q.z + q.w);
-    }
-  } else {
-    for (int t = (int)threadIdx.x; t < (int)blockIdx.x; t += kScanBlock) pre += tiles[t];
-  }
-  int offset;
-  block_exclusive_scan(pre, sh, &offset);
+  __shared__ long long sh[33];
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
   int vals[kScanItems];
   int s = 0;
@@ -209,8 +197,27 @@ __global__ __launch_bounds__(kScanBlock) void k_scan(int32_t* __restrict__ cnt, 
     vals[k] = base + k < C ? cnt[base + k] : 0;
     s += vals[k];
   }
-  int total;
-  int ex = block_exclusive_scan(s, sh, &total) + offset;
+  int pre = 0;
+  if constexpr (ONE) {
+    // all reads issued at once: tile min(t, b - 1) (in range), counted for t < b only
+    const int4* __restrict__ c4 = reinterpret_cast<const int4*>(cnt);
+    const int nb = (int)blockIdx.x;
+    if (nb > 0) {
+      int4 q[kScanOnePass - 1];
+#pragma unroll
+      for (int t = 0; t < kScanOnePass - 1; ++t) q[t] = c4[min(t, nb - 1) * (kScanTile / 4) + (int)threadIdx.x];
+#pragma unroll
+      for (int t = 0; t < kScanOnePass - 1; ++t) pre += t < nb ? (q[t].x + q[t].y) + (q[t].z + q[t].w) : 0;
+    }
+  } else {
+    for (int t = (int)threadIdx.x; t < (int)blockIdx.x; t += kScanBlock) pre += tiles[t];
+  }
+  // one block scan of pre << 32 | s: the high half totals to the tile's offset and the low
+  // half scans the tile's counts (both below 2^31, so no carry crosses the halves)
+  long long tot2;
+  const long long ex2 = block_exclusive_scan(((long long)pre << 32) | (long long)s, sh, &tot2);
+  const int offset = (int)(tot2 >> 32), total = (int)(tot2 & 0xffffffffll);
+  int ex = (int)(ex2 & 0xffffffffll) + offset;
   for (int k = 0; k < kScanItems; ++k) {
     if (base + k < C) cell_start[base + k] = ex;
     ex += vals[k];
