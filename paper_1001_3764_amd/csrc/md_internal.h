@@ -139,7 +139,7 @@ struct Views {
   unsigned long long* f_acc;   // [3N] half-shell LJ force, int64 fixed point (2^-32 kcal/mol/A); zero between uses
   int32_t* scan_tiles; // [n_tiles]
   dd* part_lj;         // [n_lj_blocks * 3]: E_lj, E_lj_shifted, W_lj
-  dd* part_bd;         // [n_atom_blocks * kBdParts]: E_b, E_a, E_d, W_b, KE, momentum xyz
+  dd* part_bd;         // [kBdParts][n_atom_blocks]: E_b, E_a, E_d, W_b, KE, momentum xyz
   double* thermo;      // [n_boxes * kThermo] integrator state per box (ThermoSlot)
   double* energy;      // [n_boxes * kEnergySlots] per-box results
   int32_t* err;        // sticky error word

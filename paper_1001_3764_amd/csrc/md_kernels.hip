@@ -597,7 +597,7 @@ __global__ __launch_bounds__(kAtomBlock) void k_bonded(Views v, FFDev ff, double
       for (int k = 0; k < NP; ++k) {
         dd s = red[0][k];
         for (int w = 1; w < kAtomBlock / 64; ++w) s = dd_add(s, red[w][k]);
-        v.part_bd[(int64_t)blockIdx.x * kBdParts + k] = s;
+        v.part_bd[(int64_t)k * v.n_atom_blocks + blockIdx.x] = s;
       }
   }
 }
@@ -642,13 +642,28 @@ __global__ __launch_bounds__(256) void k_reduce(Views v, int update, StepOpts o)
   const int count = (B.n_atoms + kAtomBlock - 1) / kAtomBlock;
   dd q[NV];
   for (int k = 0; k < NV; ++k) q[k] = dd{0.0, 0.0};
-  for (int t = threadIdx.x; t < count; t += blockDim.x) {
-    const dd* p = v.part_bd + (int64_t)(first + t) * kBdParts;
-    q[0] = dd_add(q[0], p[4]);
-    if (COM)
-      for (int k = 0; k < 3; ++k) q[iP + k] = dd_add(q[iP + k], p[5 + k]);
-    if (ENERGY)
-      for (int k = 0; k < 4; ++k) q[iE + k] = dd_add(q[iE + k], p[k]);
+  // thread t adds partials t, t + 256, t + 512, ... in that order; the loads of kBatch of them
+  // are issued together (a partial past the end re-reads the last one and is not added), so
+  // a large box (117k partials at 30M atoms) waits for one round trip per batch, not per partial
+  constexpr int NB = iE + (ENERGY ? 4 : 0);   // bonded partials read per work-group
+  constexpr int kBatch = NB <= 4 ? 8 : 4;
+  for (int t0 = threadIdx.x; t0 < count; t0 += blockDim.x * kBatch) {
+    dd r[kBatch][NB];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      // partial k of block j at part_bd[k * n_atom_blocks + j]: consecutive lanes, consecutive blocks
+      const dd* p = v.part_bd + first + min(t0 + u * (int)blockDim.x, count - 1);
+      const int64_t nb = v.n_atom_blocks;
+      r[u][0] = p[4 * nb];
+      if (COM)
+        for (int k = 0; k < 3; ++k) r[u][iP + k] = p[(5 + k) * nb];
+      if (ENERGY)
+        for (int k = 0; k < 4; ++k) r[u][iE + k] = p[k * nb];
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u)
+      if (t0 + u * (int)blockDim.x < count)
+        for (int k = 0; k < NB; ++k) q[k] = dd_add(q[k], r[u][k]);
   }
   if (ENERGY) {
     const int lfirst = B.lj_blk_off;
