@@ -43,6 +43,27 @@ def test_bins_bit_exact(ff, melt, R):
     s.close()
 
 
+@pytest.mark.parametrize("M", [40, 41])
+def test_bins_bit_exact_at_the_scan_path_boundary(ff, melt, M):
+    """40^3 = 64,000 cells fill 16 scan tiles of 4,096 (the one-launch scan, whose last block sums
+    the counts of 15 tiles); 41^3 = 68,921 fill 17 (tile totals first, then the scan).  The
+    melt's positions are stretched over the larger box so that every tile holds atoms."""
+    import dataclasses
+    R = 2
+    box = np.full(3, (M + 0.5) * ff["rc"] / R)
+    m = dataclasses.replace(melt, box=box, pos=melt.pos * (box / melt.box)[:, None])
+    s = make_system(m, ff, "mixed", R)
+    start, atoms = s.bins()
+    Mg, _, _ = s.grid(0)
+    assert np.all(Mg == M)
+    cell = O.cell_index(m.pos, m.box, Mg)
+    cnt, ostart, oatoms = O.bin_atoms(cell, int(np.prod(Mg)))
+    assert np.count_nonzero(np.add.reduceat(cnt, np.arange(0, cnt.size, 4096))) == -(-cnt.size // 4096)
+    np.testing.assert_array_equal(start, ostart)
+    np.testing.assert_array_equal(atoms, oatoms)
+    s.close()
+
+
 def test_wrap_and_bins_bit_exact_from_outside_the_box(ff, melt):
     """Positions shifted by whole and fractional box lengths: the GPU wrap and cell index
     must equal the oracle's bit for bit."""
