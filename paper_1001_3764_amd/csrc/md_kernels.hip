@@ -460,10 +460,17 @@ __global__ __launch_bounds__(kBondedThreads) void k_bonded(Views v, FFDev ff, do
     const int q = in_box ? (int)((p - B.atom_off) % L) : L;   // site within the chain
     const bool own = ENERGY && p >= g0 && p < g0 + kAtomBlock && in_box;
     V3<P> zero = v3<P>(0, 0, 0);
+    // the chain's bond vectors from p, each computed once: b1 = x_{p+1} - x_p,
+    // b2 = x_{p+2} - x_{p+1}, b3 = x_{p+3} - x_{p+2}; a difference taken the other way is the
+    // exact negation (subtraction, rint and the fused multiply-add are all odd in the difference)
+    V3<P> b1 = zero, b2 = zero, b3 = zero;
+    if (q + 1 < L) b1 = mi_diff<P>(xs, u, u + 1, S, B);
+    if (q + 2 < L) b2 = mi_diff<P>(xs, u + 1, u + 2, S, B);
+    if (q + 3 < L) b3 = mi_diff<P>(xs, u + 2, u + 3, S, B);
     // bond (p, p+1), Eq. (4)
     V3<P> f_b = zero;
     if (q + 1 < L) {
-      const V3<P> d = mi_diff<P>(xs, u, u + 1, S, B);      // x_{p+1} - x_p
+      const V3<P> d = b1;                                    // x_{p+1} - x_p
       const double d2 = (double)dot(d, d);
       const double r = sqrt(d2);
       const P dr = (P)(r - ff.b0);
@@ -476,8 +483,8 @@ __global__ __launch_bounds__(kBondedThreads) void k_bonded(Views v, FFDev ff, do
     // angle (p, p+1, p+2) at p+1, Eq. (5)
     V3<P> f_ai = zero, f_ak = zero;
     if (q + 2 < L) {
-      const V3<P> a = mi_diff<P>(xs, u + 1, u, S, B);      // x_i - x_j
-      const V3<P> c = mi_diff<P>(xs, u + 1, u + 2, S, B);  // x_k - x_j
+      const V3<P> a = neg(b1);                               // x_i - x_j
+      const V3<P> c = b2;                                    // x_k - x_j
       const P ac = dot(a, c), aa = dot(a, a), cc = dot(c, c);
       const V3<P> axc = cross(a, c);
       const P s = sqrt_p(dot(axc, axc));                     // |a||c| sin(theta)
@@ -494,9 +501,9 @@ __global__ __launch_bounds__(kBondedThreads) void k_bonded(Views v, FFDev ff, do
     // dihedral (p, p+1, p+2, p+3), Eq. (6), IUPAC angle
     V3<P> f_di = zero, f_dj = zero, f_dl = zero;
     if (q + 3 < L) {
-      const V3<P> rij = mi_diff<P>(xs, u + 1, u, S, B);      // x_i - x_j
-      const V3<P> rkj = mi_diff<P>(xs, u + 1, u + 2, S, B);  // x_k - x_j
-      const V3<P> rkl = mi_diff<P>(xs, u + 3, u + 2, S, B);  // x_k - x_l
+      const V3<P> rij = neg(b1);                               // x_i - x_j
+      const V3<P> rkj = b2;                                    // x_k - x_j
+      const V3<P> rkl = neg(b3);                               // x_k - x_l
       const V3<P> m = cross(rij, rkj);
       const V3<P> n = cross(rkj, rkl);
       const P mm = dot(m, m), nn = dot(n, n), kk = dot(rkj, rkj);
