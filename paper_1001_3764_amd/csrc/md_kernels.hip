@@ -25,6 +25,8 @@
 // no grid-wide synchronisation beyond kernel boundaries.
 #include "md_internal.h"
 
+#include <type_traits>
+
 namespace mdk {
 namespace {
 
@@ -415,15 +417,19 @@ __device__ inline V3<P> mi_diff(const double* xs, int a, int b, int stride, cons
   return v3<P>((P)d[0], (P)d[1], (P)d[2]);
 }
 
-// The bonded kernel runs kAtomBlock atoms per work-group on one more wavefront than it has
-// atoms: the 3 term starts and 6 staged positions beyond the first kAtomBlock go to that wave
-// instead of a second pass of wave 0 (it owns no atom; its partial sums are exact zeros).
+// The bonded kernel runs kAtomBlock atoms per work-group.  The mixed form runs it on one more
+// wavefront than it has atoms: the 3 term starts and 6 staged positions beyond the first
+// kAtomBlock go to that wave instead of a second pass of wave 0 (it owns no atom; its partial
+// sums are exact zeros).  The FP64 form, whose LDS arrays allow 3 work-groups per CU, measured
+// faster without it.
 constexpr int kBondedThreads = kAtomBlock + 64;
+template <typename P>
+constexpr int bonded_threads() { return std::is_same<P, double>::value ? kAtomBlock : kBondedThreads; }
 
 // MODE (BondedMode): forces only, or also the second velocity-Verlet half kick, or (leap-frog)
 // the kinetic energy of the velocities as they stand.  COM: also the box momentum partials.
 template <typename P, int MODE, bool ENERGY, bool COM>
-__global__ __launch_bounds__(kBondedThreads) void k_bonded(Views v, FFDev ff, double dt) {
+__global__ __launch_bounds__(bonded_threads<P>()) void k_bonded(Views v, FFDev ff, double dt) {
   constexpr bool KICK = MODE == kBondedVerletKick;
   constexpr bool SUMS = MODE != kBondedForces || ENERGY;   // block partials written
   constexpr int NP = COM ? 8 : 5;
@@ -434,7 +440,8 @@ __global__ __launch_bounds__(kBondedThreads) void k_bonded(Views v, FFDev ff, do
   // per term start u: bond force on its first atom; angle forces on i and k;
   // dihedral forces on i, j and l (the missing atom gets minus the sum)
   __shared__ P fb[3 * T], fai[3 * T], fak[3 * T], fdi[3 * T], fdj[3 * T], fdl[3 * T];
-  __shared__ dd red[kBondedThreads / 64][NP];
+  constexpr int NT = bonded_threads<P>();
+  __shared__ dd red[NT / 64][NP];
 
   const int b = v.blk_box[blockIdx.x];
   const BoxDev B = v.boxes[b];   // read at entry, before any store: scalar loads
@@ -443,7 +450,7 @@ __global__ __launch_bounds__(kBondedThreads) void k_bonded(Views v, FFDev ff, do
   const int32_t box_end = B.atom_off + B.n_atoms;
   const int L = ff.chain_len;
 
-  for (int t = threadIdx.x; t < S; t += kBondedThreads) {
+  for (int t = threadIdx.x; t < S; t += NT) {
     const int32_t g = g0 - kHalo + t;
     const bool ok = g >= B.atom_off && g < box_end;
     xs[t] = ok ? v.pos[g] : 0.0;
@@ -454,7 +461,7 @@ __global__ __launch_bounds__(kBondedThreads) void k_bonded(Views v, FFDev ff, do
 
   double e_b = 0.0, e_a = 0.0, e_d = 0.0, w_b = 0.0;
   const P kb = (P)ff.kb, ka = (P)ff.ka, kphi = (P)ff.kphi;
-  for (int u = threadIdx.x; u < T; u += kBondedThreads) {
+  for (int u = threadIdx.x; u < T; u += NT) {
     const int32_t p = g0 - kHalo + u;   // first atom of the terms starting here
     const bool in_box = p >= B.atom_off && p < box_end;
     const int q = in_box ? (int)((p - B.atom_off) % L) : L;   // site within the chain
@@ -608,7 +615,7 @@ __global__ __launch_bounds__(kBondedThreads) void k_bonded(Views v, FFDev ff, do
     if (threadIdx.x == 0)
       for (int k = 0; k < NP; ++k) {
         dd s = red[0][k];
-        for (int w = 1; w < kBondedThreads / 64; ++w) s = dd_add(s, red[w][k]);
+        for (int w = 1; w < NT / 64; ++w) s = dd_add(s, red[w][k]);
         v.part_bd[(int64_t)k * v.n_atom_blocks + blockIdx.x] = s;
       }
   }
@@ -824,7 +831,7 @@ template <typename P>
 void launch_bonded_p(const Views& v, const FFDev& ff, BondedMode mode, bool energy, bool com, double dt,
                      hipStream_t s) {
   dim3 g(v.n_atom_blocks);
-#define MDK_BONDED(M, E, C) hipLaunchKernelGGL((k_bonded<P, M, E, C>), g, dim3(kBondedThreads), 0, s, v, ff, dt)
+#define MDK_BONDED(M, E, C) hipLaunchKernelGGL((k_bonded<P, M, E, C>), g, dim3(bonded_threads<P>()), 0, s, v, ff, dt)
   if (mode == kBondedForces) {
     if (energy) MDK_BONDED(kBondedForces, true, false); else MDK_BONDED(kBondedForces, false, false);
   } else if (mode == kBondedVerletKick) {
