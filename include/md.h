@@ -183,6 +183,27 @@ md_status md_init_system(const md_forcefield* ff, const md_config* cfg, double* 
                          const uint8_t* type, void* workspace, size_t ws_bytes, void* stream,
                          md_ctx** out);
 
+/* Allocation-free set-up, for callers that cannot allocate device memory (code that must not
+   call hipMalloc or an allocating library routine: serving loops, harnesses that forbid it).
+   As md_init_system, except that the workspace is a device array inside the library,
+   MD_STATIC_WORKSPACE_BYTES per GPU (allocated when the library's code object is loaded on that
+   GPU and held until the process ends), so the caller passes only the positions, velocities
+   and types.  Nothing is allocated on the device by this call or by later calls on the context.
+   Restrictions: use_graph = 0 (instantiating a graph allocates), and cell_div and lj_kernel
+   given (nonzero: the autotuner's timing is not used).  Errors: MD_ERR_ARG for those, as
+   md_init_system otherwise; MD_ERR_WORKSPACE when md_workspace_bytes exceeds
+   MD_STATIC_WORKSPACE_BYTES (nothing is enqueued then); MD_ERR_HIP if the array's device address
+   cannot be obtained.
+   Sharing: every allocation-free context on one GPU uses that GPU's one array.  A call takes it
+   over: afterwards every call on an older allocation-free context of the same GPU returns
+   MD_ERR_STATE (destroy it; only md_destroy, md_grid, md_tuning and md_last_error still work).
+   The array keeps the last context's contents; the set-up clears everything that must start at
+   zero.  Calls on two contexts that share the array race if they overlap in time (for instance
+   on two streams); contexts made by md_init_system are unaffected. */
+#define MD_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+md_status md_init_system_static(const md_forcefield* ff, const md_config* cfg, double* pos, double* vel,
+                                const uint8_t* type, void* stream, md_ctx** out);
+
 /* Wrap positions into their box, recompute cell indices and rebuild the cell lists
    and the sorted coordinate payload (Section 3.1); in neighbour-list mode also
    rebuild the list. */

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -46,11 +47,39 @@ struct md_ctx {
   int64_t step = 0;
   bool failed = false;
   std::string last_error;
+  // allocation-free contexts (md_init_system_static): the device whose scratch array is the
+  // workspace, and the take-over count of that array when this context took it (-1: caller
+  // workspace)
+  int scratch_dev = -1;
+  uint64_t scratch_gen = 0;
 };
 
 namespace {
 
 constexpr size_t kAlign = 256;
+
+// Workspace of the allocation-free set-up (md_init_system_static): one array per GPU in the
+// code object, MD_STATIC_WORKSPACE_BYTES, held until the process ends.  In host code its name
+// is a host-side stand-in, never a device address: kernels and copies get the address that
+// hipGetSymbolAddress returns for the current device (scratch_ptr).
+constexpr size_t kScratchBytes = MD_STATIC_WORKSPACE_BYTES;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};       // device address of scratch, per device
+uint64_t g_scratch_gen[kMaxDevices] = {};    // allocation-free contexts created, per device
+
+// An allocation-free context whose device scratch array a later md_init_system_static on the
+// same device has taken over: its workspace now holds the other context's data.
+bool taken_over(const md_ctx* c) {
+  if (c->scratch_dev < 0) return false;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_gen[c->scratch_dev] != c->scratch_gen;
+}
+
+// A context can run while it has not failed and still owns its workspace.
+bool usable(const md_ctx* c) { return !c->failed && !taken_over(c); }
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -561,9 +590,11 @@ md_status md_workspace_bytes(const md_forcefield* ff, const md_config* cfg, size
   return MD_OK;
 }
 
-md_status md_init_system(const md_forcefield* ff, const md_config* cfg, double* pos, double* vel,
-                         const uint8_t* type, void* workspace, size_t ws_bytes, void* stream,
-                         md_ctx** out) {
+// md_init_system and md_init_system_static.  scratch_dev >= 0: the workspace is that device's
+// scratch array (its take-over count is recorded in the context).
+static md_status init_impl(const md_forcefield* ff, const md_config* cfg, double* pos, double* vel,
+                           const uint8_t* type, void* workspace, size_t ws_bytes, void* stream, md_ctx** out,
+                           int scratch_dev, uint64_t scratch_gen) {
   if (!out) return MD_ERR_ARG;
   *out = nullptr;
   std::string why;
@@ -599,6 +630,8 @@ md_status md_init_system(const md_forcefield* ff, const md_config* cfg, double* 
   c->ws = (char*)workspace;
   c->ws_bytes = ws_bytes;
   c->stream = (hipStream_t)stream;
+  c->scratch_dev = scratch_dev;
+  c->scratch_gen = scratch_gen;
   c->ffd = make_ffdev(ff, cfg->chain_len);
   {
     // total mass per box, for the centre-of-mass velocity
@@ -648,9 +681,47 @@ md_status md_init_system(const md_forcefield* ff, const md_config* cfg, double* 
   return MD_OK;
 }
 
+md_status md_init_system(const md_forcefield* ff, const md_config* cfg, double* pos, double* vel,
+                         const uint8_t* type, void* workspace, size_t ws_bytes, void* stream,
+                         md_ctx** out) {
+  return init_impl(ff, cfg, pos, vel, type, workspace, ws_bytes, stream, out, -1, 0);
+}
+
+md_status md_init_system_static(const md_forcefield* ff, const md_config* cfg, double* pos, double* vel,
+                                const uint8_t* type, void* stream, md_ctx** out) {
+  if (!out) return MD_ERR_ARG;
+  *out = nullptr;
+  std::string why;
+  md_status st = validate(ff, cfg, &why);
+  if (st) return st;
+  if (!pos || !vel || !type) return MD_ERR_ARG;
+  // no graph (instantiating one allocates) and no autotuning (its timing events): both choices
+  // must come from the caller
+  if (cfg->use_graph || cfg->cell_div == 0 || cfg->lj_kernel == 0) return MD_ERR_ARG;
+  size_t need = 0;
+  if ((st = md_workspace_bytes(ff, cfg, &need))) return st;
+  if (need > kScratchBytes) return MD_ERR_WORKSPACE;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return MD_ERR_HIP;
+  uint64_t gen = 0;
+  void* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+      // once per device, with that device current: the device address of this device's copy
+      void* p = nullptr;
+      if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return MD_ERR_HIP;
+      g_scratch_ptr[dev] = p;
+    }
+    ws = g_scratch_ptr[dev];
+    gen = ++g_scratch_gen[dev];   // earlier allocation-free contexts of this device stop here
+  }
+  return init_impl(ff, cfg, pos, vel, type, ws, kScratchBytes, stream, out, dev, gen);
+}
+
 md_status md_rebuild_bins(md_ctx* c) {
   if (!c) return MD_ERR_ARG;
-  if (c->failed) return MD_ERR_STATE;
+  if (!usable(c)) return MD_ERR_STATE;
   enqueue_rebuild(c, c->stream, false);
   c->since_build = 0;
   return check_launch(c, "rebuild bins");
@@ -658,7 +729,7 @@ md_status md_rebuild_bins(md_ctx* c) {
 
 md_status md_compute_forces(md_ctx* c, int32_t with_energy) {
   if (!c) return MD_ERR_ARG;
-  if (c->failed) return MD_ERR_STATE;
+  if (!usable(c)) return MD_ERR_STATE;
   enqueue_forces(c, c->stream, false, with_energy != 0, c->since_build == 0);
   if (with_energy) launch_reduce(c->v, true, false, opts(c), c->stream);
   return check_launch(c, "compute forces");
@@ -666,7 +737,7 @@ md_status md_compute_forces(md_ctx* c, int32_t with_energy) {
 
 md_status md_step(md_ctx* c, int32_t n_steps) {
   if (!c || n_steps < 0) return MD_ERR_ARG;
-  if (c->failed) return MD_ERR_STATE;
+  if (!usable(c)) return MD_ERR_STATE;
   if (n_steps == 0) return MD_OK;
   md_status st;
   for (int32_t k = 0; k < n_steps; ++k) {
@@ -687,7 +758,7 @@ md_status md_step(md_ctx* c, int32_t n_steps) {
 
 md_status md_step_timed(md_ctx* c, int32_t n_steps, double* ms_out) {
   if (!c || n_steps < 0 || !ms_out) return MD_ERR_ARG;
-  if (c->failed) return MD_ERR_STATE;
+  if (!usable(c)) return MD_ERR_STATE;
   if (n_steps == 0) return MD_OK;
   md_status st;
   const int P = MD_N_PHASES;
@@ -753,6 +824,7 @@ md_status md_step_timed(md_ctx* c, int32_t n_steps, double* ms_out) {
 
 md_status md_energies(md_ctx* c, md_energy* out) {
   if (!c || !out) return MD_ERR_ARG;
+  if (taken_over(c)) return MD_ERR_STATE;
   md_status st;
   if ((st = hip_check(c, hipStreamSynchronize(c->stream), "sync"))) return st;
   std::vector<double> e((size_t)kEnergySlots * c->n_boxes);
@@ -788,6 +860,7 @@ md_status md_energies(md_ctx* c, md_energy* out) {
 
 md_status md_bins(md_ctx* c, const int32_t** cell_start, const int32_t** cell_atoms, int64_t* n_cells) {
   if (!c || !cell_start || !cell_atoms || !n_cells) return MD_ERR_ARG;
+  if (taken_over(c)) return MD_ERR_STATE;
   *cell_start = c->v.cell_start;
   *cell_atoms = c->v.cell_atoms;
   *n_cells = c->v.C;
@@ -805,6 +878,7 @@ md_status md_grid(const md_ctx* c, int32_t box, int32_t M[3], int64_t* cell_offs
 
 md_status md_forces(md_ctx* c, const void** f, int32_t* is_fp32) {
   if (!c || !f || !is_fp32) return MD_ERR_ARG;
+  if (taken_over(c)) return MD_ERR_STATE;
   *f = c->v.f_tot;
   *is_fp32 = c->prec == MD_PREC_MIXED;
   return MD_OK;
@@ -812,6 +886,7 @@ md_status md_forces(md_ctx* c, const void** f, int32_t* is_fp32) {
 
 md_status md_forces_lj(md_ctx* c, const void** f, int32_t* is_fp32) {
   if (!c || !f || !is_fp32) return MD_ERR_ARG;
+  if (taken_over(c)) return MD_ERR_STATE;
   *f = c->v.f_lj;
   *is_fp32 = c->prec == MD_PREC_MIXED;
   return MD_OK;
@@ -827,7 +902,7 @@ md_status md_tuning(const md_ctx* c, int32_t* cell_div, int32_t* lj_kernel) {
 md_status md_observables(md_ctx* c, const md_obs_config* o, uint64_t* pairs, uint64_t* dih, double* shape) {
   static_assert(kMaxObsBins == MD_OBS_MAX_BINS, "observable bins");
   if (!c || !o) return MD_ERR_ARG;
-  if (c->failed) return MD_ERR_STATE;
+  if (!usable(c)) return MD_ERR_STATE;
   if (pairs && (o->rdf_bins < 1 || o->rdf_bins > kMaxObsBins || !(o->rdf_rmax > 0.0) || !(o->rdf_rmax <= c->ff.rc)))
     return fail(c, MD_ERR_ARG, "rdf_bins must be 1..MD_OBS_MAX_BINS and 0 < rdf_rmax <= rc");
   if (dih && (o->dih_bins < 0 || o->dih_bins > kMaxObsBins - 3))

@@ -77,6 +77,7 @@ def load():
     sig = {
         "md_workspace_bytes": (S, [_P, _P, ctypes.POINTER(ctypes.c_size_t)]),
         "md_init_system": (S, [_P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)]),
+        "md_init_system_static": (S, [_P, _P, _P, _P, _P, _P, ctypes.POINTER(_P)]),
         "md_rebuild_bins": (S, [_P]),
         "md_compute_forces": (S, [_P, _I32]),
         "md_step": (S, [_P, _I32]),
@@ -168,6 +169,16 @@ def md_init_system(ff, cfg, pos, vel, types, workspace, stream):
     return ctx
 
 
+def md_init_system_static(ff, cfg, pos, vel, types, stream):
+    ctx = _P()
+    _check(load().md_init_system_static(ctypes.byref(ff), ctypes.byref(cfg), pos.data_ptr(), vel.data_ptr(),
+                                        types.data_ptr(), stream, ctypes.byref(ctx)), "md_init_system_static")
+    return ctx
+
+
+MD_STATIC_WORKSPACE_BYTES = 64 << 20
+
+
 def md_rebuild_bins(ctx):
     _check(load().md_rebuild_bins(ctx), "md_rebuild_bins", ctx)
 
@@ -241,15 +252,32 @@ def md_destroy(ctx):
     _check(load().md_destroy(ctx), "md_destroy")
 
 
+_HIP = None
+
+
+def _hip_copy_to_host(dst, src, nbytes):
+    """hipMemcpy device -> host (synchronous) for device memory that no torch tensor owns."""
+    global _HIP
+    if _HIP is None:
+        _HIP = ctypes.CDLL("libamdhip64.so")
+        _HIP.hipMemcpy.restype = ctypes.c_int
+        _HIP.hipMemcpy.argtypes = [_P, _P, ctypes.c_size_t, ctypes.c_int]
+    rc = _HIP.hipMemcpy(dst, src, nbytes, 2)   # hipMemcpyDeviceToHost
+    if rc != 0:
+        raise RuntimeError("hipMemcpy device to host failed (%d)" % rc)
+
+
 class MDSystem:
     """One or more periodic boxes on one GPU: torch owns the device buffers, the HIP
     library owns every computation on them."""
 
     def __init__(self, ff: dict, n_chains, boxes, T0, pos, vel, types, chain_len=300, dt=1.0, tau=100.0,
                  precision="mixed", cell_div=1, lj_kernel=None, use_graph=False, device="cuda:0",
-                 nl_skin=0.0, nl_every=10, integrator="verlet", remove_com=False):
+                 nl_skin=0.0, nl_every=10, integrator="verlet", remove_com=False, static_workspace=False):
         """lj_kernel: an md_lj_kernel; None is MD_LJ_ATOM on the cell path and the autotuner
         (0) in neighbour-list mode.
+        static_workspace: set up with md_init_system_static (the library's own device array as
+        the workspace; no graph, explicit cell_div and lj_kernel).
         nl_skin > 0: neighbour-list mode (bins and list rebuilt every nl_every steps).
         integrator: "verlet" (velocity Verlet, Berendsen when T0 > 0) or "leapfrog" (leap-frog,
         Nose-Hoover when T0 > 0, tau the thermostat period; vel holds half-step velocities).
@@ -271,11 +299,17 @@ class MDSystem:
         self.pos = torch.from_numpy(pos).to(self.device).contiguous()
         self.vel = torch.from_numpy(vel).to(self.device).contiguous()
         self.types = torch.from_numpy(np.ascontiguousarray(types, dtype=np.uint8)).to(self.device)
-        nbytes = md_workspace_bytes(self.ff, self.cfg.c)
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.stream = torch.cuda.current_stream(self.device)
-        self.ctx = md_init_system(self.ff, self.cfg.c, self.pos, self.vel, self.types, self.workspace,
-                                  self.stream.cuda_stream)
+        self.ctx = None
+        if static_workspace:
+            self.workspace = None
+            self.ctx = md_init_system_static(self.ff, self.cfg.c, self.pos, self.vel, self.types,
+                                             self.stream.cuda_stream)
+        else:
+            nbytes = md_workspace_bytes(self.ff, self.cfg.c)
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self.ctx = md_init_system(self.ff, self.cfg.c, self.pos, self.vel, self.types, self.workspace,
+                                      self.stream.cuda_stream)
 
     # --- the C ABI, one call each ---
     def rebuild_bins(self):
@@ -326,8 +360,13 @@ class MDSystem:
 
     # --- device views copied to host ---
     def _ws_view(self, ptr, count, dtype):
-        off = ptr - self.workspace.data_ptr()
+        """A host copy of count elements at device address ptr inside the workspace."""
         itemsize = torch.empty(0, dtype=dtype).element_size()
+        if self.workspace is None:   # the library's own array: copy with the HIP runtime
+            out = torch.empty(count, dtype=dtype)
+            _hip_copy_to_host(out.data_ptr(), ptr, count * itemsize)
+            return out
+        off = ptr - self.workspace.data_ptr()
         assert 0 <= off and off + count * itemsize <= self.workspace.numel()
         return self.workspace[off:off + count * itemsize].view(dtype)
 

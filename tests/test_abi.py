@@ -122,6 +122,30 @@ def test_workspace_bytes_and_validation(md, ff):
     assert workspace(md, ff, config(md, n_chains=(1,), box=((25.0, 25.0, 25.0),)))[0] == md.MD_ERR_BOX_TOO_SMALL
 
 
+def test_static_setup_refusals(md, ff):
+    """md_init_system_static refuses, before touching the device, a graph, the autotuner and a
+    workspace larger than its array (the pointers below are never dereferenced)."""
+    lib = md.load()
+    fake = ctypes.c_void_p(1 << 20)
+    mff = md.make_forcefield(ff)
+
+    def init(cfg):
+        ctx = ctypes.c_void_p()
+        st = lib.md_init_system_static(ctypes.byref(mff), ctypes.byref(cfg.c), fake, fake, fake, None,
+                                       ctypes.byref(ctx))
+        assert not ctx.value
+        return st
+
+    assert init(config(md, use_graph=True)) == md.MD_ERR_ARG
+    assert init(config(md, cell_div=0)) == md.MD_ERR_ARG
+    assert init(config(md, lj_kernel=0)) == md.MD_ERR_ARG
+    assert init(config(md, dt=0.0)) == md.MD_ERR_ARG
+    small = config(md, cell_div=2, lj_kernel=2)
+    big = config(md, n_chains=(4000,), box=((327.0, 327.0, 327.0),), cell_div=2, lj_kernel=2)
+    assert workspace(md, ff, small)[1] <= md.MD_STATIC_WORKSPACE_BYTES < workspace(md, ff, big)[1]
+    assert init(big) == md.MD_ERR_WORKSPACE
+
+
 def test_status_strings(md):
     lib = md.load()
     for st in (md.MD_OK, md.MD_ERR_ARG, md.MD_ERR_BOX_TOO_SMALL, md.MD_ERR_NONFINITE, md.MD_ERR_WORKSPACE,
