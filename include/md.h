@@ -35,6 +35,12 @@
  * detected on the host before anything is enqueued.  Errors found on the device
  * (non-finite positions or forces) set a sticky device word that the next
  * md_energies reports; the context then refuses md_step until re-initialised.
+ *
+ * Range of the mixed form.  Coordinates are held relative to their cell centre as int32
+ * fixed point (2^-25 A), so the configuration must keep (R + 2) * cell edge + nl_skin below
+ * 63 A on every box and axis (R the stencil radius; the LJ kernels shift candidates by up to
+ * R + 1 edges); md_workspace_bytes and md_init_system refuse it otherwise (MD_ERR_ARG).  Atom
+ * types are 0 or 1 (Table I's two united atoms).
  */
 #ifndef MD_H
 #define MD_H
@@ -54,9 +60,10 @@ typedef enum {
   MD_ERR_WORKSPACE = -4,      /* workspace smaller than md_workspace_bytes, or misaligned */
   MD_ERR_HIP = -6,            /* a HIP runtime call failed; md_last_error has the text */
   MD_ERR_STATE = -7,          /* the context is in an error state; re-initialise it */
-  MD_ERR_NLIST = -8           /* neighbour-list mode (device): an atom moved more than half the
-                                 skin since the last list build, or an atom had more list
-                                 neighbours than the list holds; pairs may have been missed */
+  MD_ERR_NLIST = -8           /* reserved; not returned by this version: neighbour lists are rebuilt
+                                 in the same step as soon as an atom has moved more than half the
+                                 skin, and a cell or atom whose list outgrew its capacity walks its
+                                 stencil instead, so a list never misses a pair */
 } md_status;
 
 typedef enum {
@@ -132,13 +139,15 @@ typedef struct {
   int32_t lj_kernel;          /* md_lj_kernel: 1..3 or 6 (cell path) or 4..5 (neighbour-list mode),
                                  or 0 for the autotuner (which never picks 6) */
   int32_t use_graph;          /* 1: md_step replays a captured hipGraph of the step */
-  double nl_skin;             /* > 0: neighbour-list mode.  A Verlet list of the pairs closer
-                                 than rc + nl_skin (A) is built from the bins, and the bins and
-                                 the list are rebuilt every nl_every steps instead of every step
-                                 (the paper's force path, Sections 3.1-3.2).  Every step checks
-                                 that no atom moved more than nl_skin / 2 since the build
-                                 (MD_ERR_NLIST otherwise).  0: forces from the cells every step */
-  int32_t nl_every;           /* steps between list builds, >= 1 (neighbour-list mode only) */
+  double nl_skin;             /* > 0: neighbour-list mode, the paper's force path (Sections 3.1-3.2).
+                                 A Verlet list of the pairs closer than rc + nl_skin (A) is built
+                                 from the bins.  Every step checks each atom's displacement since
+                                 the last build; when one exceeds nl_skin / 2 the bins and the list
+                                 are rebuilt in that step, before the forces (a device flag gates
+                                 the rebuild kernels, so graph replay needs no host decision).
+                                 0: forces from the cells every step */
+  int32_t nl_every;           /* neighbour-list mode: >= 1 also rebuilds every nl_every steps
+                                 (the paper rebuilds every 10), 0 only on displacement */
   int32_t integrator;         /* md_integrator */
   int32_t remove_com;         /* 1: after every step subtract each box's centre-of-mass velocity
                                  sum(m v) / sum(m) (after the drift, before the thermostat reads
@@ -165,14 +174,19 @@ typedef struct {
 
 typedef struct md_ctx md_ctx;
 
-/* Bytes of device workspace the configuration needs (for cell_div = 0 or
-   lj_kernel = 0, the largest over the autotuner's candidates).  Never fails for a
-   valid configuration; MD_ERR_ARG / MD_ERR_BOX_TOO_SMALL otherwise. */
+/* Input of initial conditions (Fig. 1): bytes of device workspace the configuration needs
+   (for cell_div = 0 or lj_kernel = 0, the largest over the autotuner's candidates).  Never
+   fails for a valid configuration; MD_ERR_ARG (including a mixed configuration outside the
+   fixed-point range) / MD_ERR_BOX_TOO_SMALL (fewer than 2R + 1 cells of edge >= rc / R on an
+   axis for every stencil radius R) otherwise. */
 md_status md_workspace_bytes(const md_forcefield* ff, const md_config* cfg, size_t* bytes);
 
-/* Validates the configuration, copies the small per-box tables to the device,
+/* Input of initial conditions (Fig. 1; positions, velocities, types and the chain topology of
+   Section 2): validates the configuration, copies the small per-box tables to the device,
    builds the bins and computes the forces at the initial positions (so the first
-   half-kick has a force), and, when use_graph = 1, captures the step graph.
+   half-kick has a force), stores the end-to-end vectors as the autocorrelation's reference,
+   and, when use_graph = 1, captures the step graph.  MD_ERR_ARG also for an atom type
+   other than 0 or 1 (read from the device type array).
    pos, vel: device FP64 [3 * N], updated in place by md_step.
    type:     device uint8 [N], 0 or 1.
    workspace: device, >= md_workspace_bytes, 256-byte aligned.
@@ -204,20 +218,21 @@ md_status md_init_system(const md_forcefield* ff, const md_config* cfg, double* 
 md_status md_init_system_static(const md_forcefield* ff, const md_config* cfg, double* pos, double* vel,
                                 const uint8_t* type, void* stream, md_ctx** out);
 
-/* Wrap positions into their box, recompute cell indices and rebuild the cell lists
-   and the sorted coordinate payload (Section 3.1); in neighbour-list mode also
-   rebuild the list. */
+/* Binning (Section 3.1): wrap positions into their box, recompute cell indices and rebuild
+   the cell lists and the sorted coordinate payload; in neighbour-list mode also rebuild the
+   list.  Enqueues only. */
 md_status md_rebuild_bins(md_ctx* ctx);
 
-/* Forces at the positions of the last bin rebuild: LJ (Section 3.2) plus bonded
-   (Section 3.3); with_energy != 0 also evaluates the per-box energies and virial
-   (read them with md_energies). */
+/* Forces (Sections 3.2-3.3): at the positions of the last bin rebuild (in neighbour-list
+   mode, the current positions through the list), LJ (Eq. 2) plus bonded (Eqs. 4-6);
+   with_energy != 0 also evaluates the per-box energies and virial (read them with
+   md_energies).  Enqueues only. */
 md_status md_compute_forces(md_ctx* ctx, int32_t with_energy);
 
-/* Advance every box by n_steps (>= 0) steps of the configured integrator with the bins rebuilt
-   every step (in neighbour-list mode: every nl_every steps, counted from the last
-   build, together with the list); energies are evaluated on the last step.  Enqueues
-   only. */
+/* The MD loop (Section 3.4, Fig. 1): advance every box by n_steps (>= 0) steps of the
+   configured integrator with the bins rebuilt every step (in neighbour-list mode: when an atom
+   has moved more than half the skin, or every nl_every steps, together with the list);
+   energies are evaluated on the last step.  Enqueues only. */
 md_status md_step(md_ctx* ctx, int32_t n_steps);
 
 /* Phases timed by md_step_timed. */
@@ -238,34 +253,41 @@ enum {
    check and the payload refresh on the steps between builds, and the scan, scatter,
    rank and list phases are empty on those steps. */
 
-/* Same as md_step but launched without the graph and with a pair of HIP events
-   around every phase on the context's stream; adds each phase's summed duration in
-   milliseconds to ms_out[MD_N_PHASES].  Synchronises the stream before returning. */
+/* Measurement of the MD loop (Section 4's per-kernel timings): the same as md_step but
+   launched without the graph and with a pair of HIP events around every phase on the
+   context's stream; adds each phase's summed duration in milliseconds to
+   ms_out[MD_N_PHASES].  Synchronises the stream before returning. */
 md_status md_step_timed(md_ctx* ctx, int32_t n_steps, double* ms_out);
 
-/* Synchronises the stream and copies the per-box results to out_host[n_boxes].
-   Returns MD_ERR_NONFINITE if the device flagged a non-finite value (sticky). */
+/* Output of the step's energies (Section 3.4: kinetic energy and temperature; Eqs. 2, 4-6:
+   the potential energies; the virial): synchronises the stream and copies the per-box results
+   to out_host[n_boxes] (host).  Returns MD_ERR_NONFINITE if the device flagged a non-finite
+   value (sticky: the context then refuses further steps), MD_ERR_STATE for an
+   allocation-free context whose array was taken over, MD_ERR_HIP if a copy fails. */
 md_status md_energies(md_ctx* ctx, md_energy* out_host);
 
-/* Device views of the cell lists of the last rebuild: cell_start[n_cells + 1]
-   (exclusive prefix sums, cells of all boxes concatenated box by box) and
-   cell_atoms[N] (global atom indices, ascending within a cell). */
+/* The bins of Section 3.1 (the paper's cell table, here in compressed form): device views of
+   the cell lists of the last rebuild, cell_start[n_cells + 1] (exclusive prefix sums, cells of
+   all boxes concatenated box by box) and cell_atoms[N] (global atom indices, ascending within a
+   cell).  Owned by the workspace; valid until the next rebuild. */
 md_status md_bins(md_ctx* ctx, const int32_t** cell_start, const int32_t** cell_atoms,
                   int64_t* n_cells);
 
-/* Grid of one box: cells per dimension (cell index = kx + M[0] * (ky + M[1] * kz)),
-   and the offsets of its first cell and first atom in the concatenated arrays. */
+/* The grid of Section 3.1 for one box: cells per dimension (cell index = kx + M[0] * (ky +
+   M[1] * kz)), and the offsets of its first cell and first atom in the concatenated arrays. */
 md_status md_grid(const md_ctx* ctx, int32_t box, int32_t M[3], int64_t* cell_offset,
                   int64_t* atom_offset);
 
-/* Device view of the total force of the last evaluation, SoA [3 * N], FP32 when
-   *is_fp32 = 1 (mixed precision) else FP64; kcal/mol/A. */
+/* The force of Sections 3.2-3.3: device view of the total force of the last evaluation,
+   SoA [3 * N], FP32 when *is_fp32 = 1 (mixed precision) else FP64; kcal/mol/A.  Owned by the
+   workspace; valid until the next evaluation. */
 md_status md_forces(md_ctx* ctx, const void** f, int32_t* is_fp32);
 
-/* Device view of the LJ part of the force alone, same layout as md_forces. */
+/* The Lennard-Jones part (Section 3.2, Eq. 2) of the force alone, same layout as md_forces. */
 md_status md_forces_lj(md_ctx* ctx, const void** f, int32_t* is_fp32);
 
-/* The stencil radius and LJ kernel in use (what the autotuner chose, if asked). */
+/* The cell size of Section 3.1 (edge >= rc / cell_div) and the LJ kernel in use (what the
+   autotuner chose, if asked).  Host only. */
 md_status md_tuning(const md_ctx* ctx, int32_t* cell_div, int32_t* lj_kernel);
 
 /* Structural observables of Section 5 (Figs. 8-10, 12, 15). */
@@ -294,6 +316,19 @@ typedef struct {
    those of the last list build, which still cover every pair within rc).  Enqueues only. */
 md_status md_observables(md_ctx* ctx, const md_obs_config* cfg, uint64_t* pair_counts,
                          uint64_t* dihedral_counts, double* chain_shape);
+
+/* End-to-end vector autocorrelation (Section 5, Fig. 8).  md_ree_reference stores every
+   chain's end-to-end vector (the sum of its minimum-imaged bonds, first atom to last) as the
+   reference, time zero (md_init_system stores the initial ones).  md_ree_acf writes, per box,
+   acf[b] = sum_c R_c . R_c(0) / sum_c |R_c(0)|^2 over the box's chains (acf: device double
+   [n_boxes], caller-owned; sums in a fixed order, double-double).  Both enqueue only. */
+md_status md_ree_reference(md_ctx* ctx);
+md_status md_ree_acf(md_ctx* ctx, double* acf);
+
+/* Neighbour-list mode: the number of list rebuilds the steps have made since init (those of
+   md_init_system and md_rebuild_bins not counted), for monitoring the rebuild rate; 0 on the
+   cell path.  Synchronises the stream. */
+md_status md_list_builds(md_ctx* ctx, int64_t* builds);
 
 /* Frees the host-side context and its graph; device buffers stay with the caller. */
 md_status md_destroy(md_ctx* ctx);

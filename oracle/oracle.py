@@ -85,6 +85,7 @@ def lib():
             "ora_pair_histogram": (ctypes.c_int, [I64, I32, I32, P, P, P, P, P, D, I32, P]),
             "ora_dihedral_stats": (ctypes.c_int, [I64, I32, P, P, P, P, I32, P, P]),
             "ora_chain_shape": (ctypes.c_int, [P, I64, I32, P, P, P, P, P, P]),
+            "ora_ree_acf": (ctypes.c_int, [I64, I32, P, P, P, P, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -341,6 +342,18 @@ def chain_shape(ff, pos, types, box, chain_len):
     return out
 
 
+def ree_acf(pos0, pos, box, chain_len):
+    """End-to-end vector autocorrelation sum_c R_c(t).R_c(0) / sum_c |R_c(0)|^2 (Fig. 8) between
+    the positions pos0 (reference time) and pos."""
+    a, b = _soa(pos0), _soa(pos)
+    assert a.shape == b.shape
+    L = _box(box)
+    out = D()
+    _check(lib().ora_ree_acf(a.shape[1], chain_len, _p(a[0]), _p(a[1]), _p(a[2]), _p(b[0]), _p(b[1]), _p(b[2]),
+                             _p(L), ctypes.byref(out)), "ora_ree_acf")
+    return out.value
+
+
 def run(ff, pos, vel, frc, types, box, chain_len, n_steps, dt=1.0, tau=100.0, T0=0.0, M=None, R=1,
         remove_com=False):
     """Advance copies of (pos, vel, frc) by n_steps; frc must be the force at pos."""
@@ -361,7 +374,7 @@ def run(ff, pos, vel, frc, types, box, chain_len, n_steps, dt=1.0, tau=100.0, T0
     return p, v, f, {**e.as_dict(), "e_kin": ke.value, "temperature": T.value}
 
 
-__all__ = ["build", "lib", "make_ff", "set_threads", "grid_dims", "wrap", "cell_index", "bin_atoms",
+__all__ = ["build", "lib", "make_ff", "ree_acf", "set_threads", "grid_dims", "wrap", "cell_index", "bin_atoms",
            "lj_brute", "lj_cells", "bonded", "forces", "chain_terms", "compensated_sum", "kinetic", "bond_term",
            "angle_term", "dihedral_term", "run", "run_leapfrog", "com_velocity", "pair_histogram", "dihedral_stats",
            "chain_shape"]

@@ -682,3 +682,30 @@ int ora_chain_shape(const ora_ff* ff, int64_t n, int32_t chain_len, const double
   free(u);
   return 0;
 }
+
+/* The end-to-end vector of the chain starting at atom a: its bonds, minimum-imaged, summed
+   from the first to the last. */
+static void end_to_end(int64_t a, int32_t chain_len, const double* x, const double* y, const double* z,
+                       const double L[3], double r[3]) {
+  r[0] = r[1] = r[2] = 0.0;
+  for (int32_t p = 1; p < chain_len; ++p) {
+    r[0] += min_image(x[a + p] - x[a + p - 1], L[0]);
+    r[1] += min_image(y[a + p] - y[a + p - 1], L[1]);
+    r[2] += min_image(z[a + p] - z[a + p - 1], L[2]);
+  }
+}
+
+int ora_ree_acf(int64_t n, int32_t chain_len, const double* x0, const double* y0, const double* z0,
+                const double* x, const double* y, const double* z, const double L[3], double* acf) {
+  if (n <= 0 || chain_len < 2 || n % chain_len || !acf) return -1;
+  nsum num = {0, 0}, den = {0, 0};
+  for (int64_t a = 0; a < n; a += chain_len) {
+    double r0[3], r[3];
+    end_to_end(a, chain_len, x0, y0, z0, L, r0);
+    end_to_end(a, chain_len, x, y, z, L, r);
+    nadd(&num, dot3(r, r0));
+    nadd(&den, dot3(r0, r0));
+  }
+  *acf = nval(&num) / nval(&den);
+  return 0;
+}

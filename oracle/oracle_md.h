@@ -23,8 +23,8 @@
  *     COM-removal timing of Section 4; translation only, see ora_integ);
  *   - the structural observables of Section 5: the pair-distance histogram behind the
  *     radial distribution function (Fig. 10), the dihedral (conformation) distribution
- *     and trans fraction (Figs. 9, 15), and per-chain radius of gyration and end-to-end
- *     vector (Figs. 8, 12).
+ *     and trans fraction (Figs. 9, 15), per-chain radius of gyration and end-to-end
+ *     vector (Figs. 8, 12), and the autocorrelation of the end-to-end vectors (Fig. 8).
  *
  * Units: Angstrom, fs, g/mol, kcal/mol, K.  Every array is caller-owned host
  * memory; coordinates are structure-of-arrays.  Functions return 0 on success and
@@ -189,6 +189,15 @@ int ora_dihedral_stats(int64_t n, int32_t chain_len, const double* x, const doub
    end-to-end vector u_last - u_first.  out[4 c] = Rg^2 (A^2), out[4 c + 1..3] = R_ee (A). */
 int ora_chain_shape(const ora_ff* ff, int64_t n, int32_t chain_len, const double* x, const double* y,
                     const double* z, const uint8_t* type, const double L[3], double* out);
+
+/* End-to-end vector autocorrelation (Section 5, Fig. 8): the normalised correlation of each
+   chain's end-to-end vector with its value at a reference time, averaged over the chains,
+   acf = sum_c R_c(t) . R_c(0) / sum_c |R_c(0)|^2.  Each R is the sum of the chain's
+   minimum-imaged bond vectors, first atom to last (as ora_chain_shape); the two sums are
+   compensated.  (x0, y0, z0): positions at the reference time; (x, y, z): at time t.
+   *acf is written. */
+int ora_ree_acf(int64_t n, int32_t chain_len, const double* x0, const double* y0, const double* z0,
+                const double* x, const double* y, const double* z, const double L[3], double* acf);
 
 #ifdef __cplusplus
 }

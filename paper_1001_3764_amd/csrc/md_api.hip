@@ -43,7 +43,7 @@ struct md_ctx {
   std::vector<double> box_mass;   // total mass of each box (from the types at init)
   double nl_skin = 0.0;      // > 0: neighbour-list mode
   int nl_every = 1;
-  int since_build = 0;       // steps since the last list build
+  int since_build = 0;       // steps since the last forced list build (nl_every > 0)
   int64_t step = 0;
   bool failed = false;
   std::string last_error;
@@ -128,7 +128,7 @@ md_status validate(const md_forcefield* ff, const md_config* cfg, std::string* w
   }
   if (cfg->remove_com != 0 && cfg->remove_com != 1) { *why = "remove_com must be 0 or 1"; return MD_ERR_ARG; }
   if (!(cfg->nl_skin >= 0.0) || !std::isfinite(cfg->nl_skin)) { *why = "nl_skin must be >= 0"; return MD_ERR_ARG; }
-  if (cfg->nl_skin > 0.0 && cfg->nl_every < 1) { *why = "nl_every must be >= 1"; return MD_ERR_ARG; }
+  if (cfg->nl_skin > 0.0 && cfg->nl_every < 0) { *why = "nl_every must be >= 0"; return MD_ERR_ARG; }
   if (cfg->nl_skin > 0.0 && cfg->cell_div > kTileMaxR) { *why = "neighbour lists need cell_div <= 2"; return MD_ERR_ARG; }
   int64_t N = 0;
   for (int b = 0; b < cfg->n_boxes; ++b) {
@@ -166,6 +166,23 @@ bool grid_ok(const md_forcefield* ff, const md_config* cfg, int R) {
   return cells <= kMaxScanTiles * kScanTile && cells < ((int64_t)1 << 31);
 }
 
+// Mixed precision stores coordinates relative to their cell centre as int32 fixed point in
+// units of 2^-25 A, and the LJ kernels take differences of such values shifted by up to R cell
+// edges, or R + 1 for the padding sentinel: |x_i - x_j| in those units is at most
+// (R + 2) edge + skin (the list payload drifts by up to half the skin on each side), which must
+// stay below 2^31 (64 A; kept to 63 A).
+bool payload_ok(const md_forcefield* ff, const md_config* cfg, int R) {
+  if (cfg->precision != MD_PREC_MIXED) return true;
+  const double skin = cfg->nl_skin > 0.0 ? cfg->nl_skin : 0.0;
+  for (int b = 0; b < cfg->n_boxes; ++b)
+    for (int d = 0; d < 3; ++d) {
+      const double L = cfg->box[3 * b + d];
+      const int M = cells_per_dim(L, R, cell_reach(ff, cfg));
+      if (M < 1 || (R + 2) * (L / M) + skin >= 63.0) return false;
+    }
+  return true;
+}
+
 struct Plan {
   int64_t N = 0, C = 0;
   int32_t n_boxes = 0, n_atom_blocks = 0, n_lj_blocks = 0, n_tiles = 0;
@@ -173,6 +190,7 @@ struct Plan {
   int64_t nl_entries = 0;
   bool half = false;                        // half-shell LJ: fixed-point force accumulators
   int prec = 0;
+  int chain_len = 1;
   std::vector<BoxDev> boxes;
 };
 
@@ -205,6 +223,7 @@ Plan make_plan(const md_forcefield* ff, const md_config* cfg, int R, int kernel)
   Plan p;
   p.n_boxes = cfg->n_boxes;
   p.prec = cfg->precision;
+  p.chain_len = cfg->chain_len;
   const bool nl = cfg->nl_skin > 0.0;
   p.half = !nl && kernel == MD_LJ_HALFSHELL;
   if (nl) {
@@ -296,6 +315,9 @@ size_t carve(const Plan& p, char* base, Views* v) {
   t.energy = (double*)take(8 * kEnergySlots * (size_t)p.n_boxes);
   t.err = (int32_t*)take(4);
   t.obs_part = (uint32_t*)take(4 * (size_t)kObsBlocks * kMaxObsBins);
+  t.shift_tab = take((p.prec == MD_PREC_MIXED ? 12 : 24) * (size_t)kShiftSlots * p.n_boxes);
+  t.ree0 = (double*)take(24 * (size_t)(p.N / p.chain_len));
+  t.ree_part = (double*)take(16 * (size_t)(p.N / p.chain_len));
   if (p.nl_cap) {
     t.nl_cap = p.nl_cap;
     t.n_cell_blocks = p.n_cell_blocks;
@@ -305,6 +327,8 @@ size_t carve(const Plan& p, char* base, Views* v) {
     t.x_build = (double*)take(24 * (size_t)p.N);
     t.slot_of = (int32_t*)take(4 * (size_t)p.N);
     t.pay_cur = take(psz * (size_t)p.N);
+    t.nl_flag = (int32_t*)take(4);
+    t.nl_builds = (unsigned long long*)take(8);
   }
   if (v) *v = t;
   return off;
@@ -354,6 +378,12 @@ FFDev make_ffdev(const md_forcefield* ff, int chain_len) {
 }
 
 md_status check_launch(md_ctx* c, const char* what) { return hip_check(c, hipGetLastError(), what); }
+
+// The end-to-end vectors of every chain: stored as the reference (reference), or correlated
+// with it into out[n_boxes] (device).
+void enqueue_ree(md_ctx* c, bool reference, double* out) {
+  for (int b = 0; b < c->n_boxes; ++b) launch_ree(c->v, b, c->n_chains[b], c->chain_len, reference, out, c->stream);
+}
 
 StepOpts opts(const md_ctx* c) {
   StepOpts o;
@@ -407,6 +437,33 @@ md_status configure(md_ctx* c, const md_config* cfg, int R, int kernel) {
       (st = hip_check(c, hipMemcpy((void*)v.cell_blk_box, cb.data(), 4 * cb.size(), hipMemcpyHostToDevice),
                       "upload list build block table")))
     return st;
+  if (R <= kTileMaxR) {
+    // stencil shifts per box in the payload's units, and the sentinel slot
+    const int W = 2 * R + 1;
+    std::vector<int32_t> qi((size_t)3 * kShiftSlots * p.n_boxes, 0);
+    std::vector<double> qd((size_t)3 * kShiftSlots * p.n_boxes, 0.0);
+    for (int b = 0; b < p.n_boxes; ++b)
+      for (int code = 0; code < kShiftSlots; ++code) {
+        int o[3] = {R + 1, R + 1, 0};   // the sentinel
+        if (code < W * W * W) {
+          o[0] = code % W - R;
+          o[1] = code / W % W - R;
+          o[2] = code / (W * W) - R;
+        } else if (code != kSentinelCode) {
+          continue;
+        }
+        const size_t at = ((size_t)b * kShiftSlots + code) * 3;
+        for (int d = 0; d < 3; ++d) {
+          qi[at + d] = o[d] * p.boxes[b].edge_q[d];
+          qd[at + d] = o[d] * p.boxes[b].edge[d];
+        }
+      }
+    const bool mixed = p.prec == MD_PREC_MIXED;
+    if ((st = hip_check(c, hipMemcpy(const_cast<void*>(v.shift_tab), mixed ? (const void*)qi.data() : (const void*)qd.data(),
+                                     mixed ? 4 * qi.size() : 8 * qd.size(), hipMemcpyHostToDevice),
+                        "upload stencil shifts")))
+      return st;
+  }
   std::vector<double> th((size_t)kThermo * p.n_boxes, 0.0);
   for (int b = 0; b < p.n_boxes; ++b) th[(size_t)b * kThermo + kThPre] = th[(size_t)b * kThermo + kThPost] = 1.0;
   if ((st = hip_check(c, hipMemcpy(v.thermo, th.data(), 8 * th.size(), hipMemcpyHostToDevice),
@@ -415,6 +472,10 @@ md_status configure(md_ctx* c, const md_config* cfg, int R, int kernel) {
   launch_fill_i32(v.cnt, p.C, 0, c->stream);
   launch_fill_i32(v.err, 1, 0, c->stream);
   if (v.f_acc) launch_fill_i32((int32_t*)v.f_acc, 6 * p.N, 0, c->stream);
+  if (v.nl_flag) {
+    launch_fill_i32(v.nl_flag, 1, 0, c->stream);
+    launch_fill_i32((int32_t*)v.nl_builds, 2, 0, c->stream);
+  }
   launch_fill_f64(v.energy, kEnergySlots * (int64_t)p.n_boxes, 0.0, c->stream);
   if ((st = check_launch(c, "clear workspace"))) return st;
   c->v = v;
@@ -442,33 +503,42 @@ BondedMode bonded_mode(const md_ctx* c, bool step) {
   return c->integrator == MD_INT_LEAPFROG_NH ? kBondedLeapfrog : kBondedVerletKick;
 }
 
-// build_step: the payload of the last rebuild is current (neighbour-list mode).
 // kick: part of a step (the bonded kernel then kicks or reads the velocities).
-void enqueue_forces(md_ctx* c, hipStream_t s, bool kick, bool energy, bool build_step = true) {
+void enqueue_forces(md_ctx* c, hipStream_t s, bool kick, bool energy) {
   const bool fp32 = c->prec == MD_PREC_MIXED;
   if (nl_mode(c))
-    launch_lj_nl(c->v, c->ffd, fp32, c->lj_kernel, energy, build_step, s);
+    launch_lj_nl(c->v, c->ffd, fp32, c->lj_kernel, energy, s);
   else
     launch_lj(c->v, c->ffd, fp32, c->lj_kernel, energy, s);
   launch_bonded(c->v, c->ffd, fp32, bonded_mode(c, kick), energy, kick && c->remove_com, c->dt, s);
 }
 
-// One step.  build: rebuild bins and list (always true for the cell path).
-void enqueue_step(md_ctx* c, hipStream_t s, bool energy, bool build = true) {
-  if (nl_mode(c) && !build) {
-    launch_nl_integrate(c->v, opts(c), c->ffd, c->prec == MD_PREC_MIXED, s);
-    enqueue_forces(c, s, true, energy, false);
+// One step.  Cell path: bins rebuilt, then forces.  Neighbour-list mode: the update raises the
+// device's rebuild flag when an atom has moved more than half the skin since the last build (or
+// always, force_build), and the bin and list kernels that follow do their work only when it is
+// raised, so one captured sequence serves every step; the reduction clears the flag.
+void enqueue_step(md_ctx* c, hipStream_t s, bool energy, bool force_build = false) {
+  const bool fp32 = c->prec == MD_PREC_MIXED;
+  if (nl_mode(c)) {
+    const int32_t* gate = c->v.nl_flag;
+    launch_nl_integrate(c->v, opts(c), c->ffd, fp32, force_build, s);
+    launch_bin_count(c->v, false, opts(c), c->ffd, fp32, s, gate);
+    launch_scan(c->v, s, gate);
+    launch_scatter(c->v, s, gate);
+    launch_rank_payload(c->v, fp32, s, gate);
+    launch_nl_build(c->v, c->ffd, fp32, c->lj_kernel, s, gate);
   } else {
     enqueue_rebuild(c, s, true);
-    enqueue_forces(c, s, true, energy, true);
   }
+  enqueue_forces(c, s, true, energy);
   launch_reduce(c->v, energy, true, opts(c), s);
 }
 
-// Whether the next step rebuilds bins and list (a list serves nl_every force evaluations).
-bool next_step_builds(const md_ctx* c) { return !nl_mode(c) || c->since_build + 1 >= c->nl_every; }
+// Neighbour-list mode with nl_every > 0: whether the next step rebuilds regardless of the
+// displacements (nl_every steps after the last such build).
+bool next_step_forced(const md_ctx* c) { return nl_mode(c) && c->nl_every > 0 && c->since_build + 1 >= c->nl_every; }
 
-void advance_build_counter(md_ctx* c, bool built) { c->since_build = built ? 0 : c->since_build + 1; }
+void advance_build_counter(md_ctx* c, bool forced) { c->since_build = forced ? 0 : c->since_build + 1; }
 
 void destroy_graphs(md_ctx* c) {
   for (int k = 0; k < 4; ++k) {
@@ -487,7 +557,7 @@ md_status capture_graphs(md_ctx* c) {
   for (int k = 0; k < (nl_mode(c) ? 4 : 2); ++k) {
     if ((st = hip_check(c, hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal), "begin capture")))
       return st;
-    enqueue_step(c, c->cap, (k & 1) != 0, !nl_mode(c) || k >= 2);
+    enqueue_step(c, c->cap, (k & 1) != 0, k >= 2);
     hipError_t le = hipGetLastError();
     hipError_t e = hipStreamEndCapture(c->cap, &c->graph[k]);
     if ((st = hip_check(c, le, "launch during capture"))) return st;
@@ -510,7 +580,7 @@ md_status autotune(md_ctx* c, const md_config* cfg, int* bestR, int* bestK) {
   if (cfg->cell_div) Rs.push_back(cfg->cell_div);
   else
     for (int R = 1; R <= 2; ++R)
-      if (grid_ok(&c->ff, cfg, R)) Rs.push_back(R);
+      if (grid_ok(&c->ff, cfg, R) && payload_ok(&c->ff, cfg, R)) Rs.push_back(R);
   if (cfg->nl_skin > 0.0) {
     if (cfg->lj_kernel) {
       Ks.push_back(cfg->lj_kernel);
@@ -545,7 +615,7 @@ md_status autotune(md_ctx* c, const md_config* cfg, int* bestR, int* bestK) {
         // neighbour lists: one build serves several force evaluations (all of them from the
         // build's payload: nothing has refreshed the per-step payload here)
         if (rep == 0 || !nl_mode(c)) enqueue_rebuild(c, c->stream, false);
-        enqueue_forces(c, c->stream, false, false, true);
+        enqueue_forces(c, c->stream, false, false);
       }
       (void)hipEventRecord(e1, c->stream);
       if ((st = hip_check(c, hipEventSynchronize(e1), "autotune sync"))) break;
@@ -572,11 +642,13 @@ md_status md_workspace_bytes(const md_forcefield* ff, const md_config* cfg, size
   md_status st = validate(ff, cfg, &why);
   if (st) return st;
   size_t best = 0;
-  bool any = false;
+  bool any = false, grid_fits = false;
   for (int R = 1; R <= 3; ++R) {
     if (cfg->cell_div && cfg->cell_div != R) continue;
     if (!cfg->cell_div && R > 2) continue;
     if (!grid_ok(ff, cfg, R)) continue;
+    grid_fits = true;
+    if (!payload_ok(ff, cfg, R)) continue;
     for (int K = 1; K <= MD_LJ_HALFSHELL; ++K) {
       if (cfg->lj_kernel ? cfg->lj_kernel != K : K == MD_LJ_HALFSHELL) continue;
       if ((cfg->nl_skin > 0.0) != (K == MD_LJ_NLIST || K == MD_LJ_NLIST_TILE)) continue;
@@ -585,7 +657,7 @@ md_status md_workspace_bytes(const md_forcefield* ff, const md_config* cfg, size
       any = true;
     }
   }
-  if (!any) return MD_ERR_BOX_TOO_SMALL;
+  if (!any) return grid_fits ? MD_ERR_ARG : MD_ERR_BOX_TOO_SMALL;   // ARG: the int32 payload would overflow
   *bytes = best;
   return MD_OK;
 }
@@ -604,6 +676,7 @@ static md_status init_impl(const md_forcefield* ff, const md_config* cfg, double
   if (((uintptr_t)workspace) % kAlign) return MD_ERR_WORKSPACE;
   if (cfg->cell_div && !grid_ok(ff, cfg, cfg->cell_div)) return MD_ERR_BOX_TOO_SMALL;
   if (!cfg->cell_div && !grid_ok(ff, cfg, 1)) return MD_ERR_BOX_TOO_SMALL;
+  if (cfg->cell_div && !payload_ok(ff, cfg, cfg->cell_div)) return MD_ERR_ARG;
   if (cfg->lj_kernel >= MD_LJ_CELLTILE && cfg->cell_div > kTileMaxR) return MD_ERR_ARG;
   size_t need = 0;
   if ((st = md_workspace_bytes(ff, cfg, &need))) return st;
@@ -645,11 +718,18 @@ static md_status init_impl(const md_forcefield* ff, const md_config* cfg, double
       delete c;
       return st;
     }
+    for (int64_t i = 0; i < c->N; ++i)
+      if (ht[i] > 1) {   // the force field has two atom types (Table I: CH2, CH3)
+        std::fprintf(stderr, "md_init_system: atom %lld has type %d (types are 0 and 1)\n", (long long)i,
+                     (int)ht[i]);
+        delete c;
+        return MD_ERR_ARG;
+      }
     int64_t a = 0;
     for (int b = 0; b < cfg->n_boxes; ++b) {
       const int64_t n = (int64_t)cfg->n_chains[b] * cfg->chain_len;
       double m = 0.0;
-      for (int64_t i = 0; i < n; ++i) m += ff->mass[ht[a + i] & 1];
+      for (int64_t i = 0; i < n; ++i) m += ff->mass[ht[a + i]];
       c->box_mass.push_back(m);
       a += n;
     }
@@ -666,6 +746,7 @@ static md_status init_impl(const md_forcefield* ff, const md_config* cfg, double
     enqueue_rebuild(c, c->stream, false);
     enqueue_forces(c, c->stream, false, true);
     launch_reduce(c->v, true, false, opts(c), c->stream);
+    enqueue_ree(c, true, nullptr);   // the end-to-end autocorrelation's reference: the initial state
     st = check_launch(c, "initial forces");
   }
   if (!st && c->use_graph) st = capture_graphs(c);
@@ -730,7 +811,7 @@ md_status md_rebuild_bins(md_ctx* c) {
 md_status md_compute_forces(md_ctx* c, int32_t with_energy) {
   if (!c) return MD_ERR_ARG;
   if (!usable(c)) return MD_ERR_STATE;
-  enqueue_forces(c, c->stream, false, with_energy != 0, c->since_build == 0);
+  enqueue_forces(c, c->stream, false, with_energy != 0);
   if (with_energy) launch_reduce(c->v, true, false, opts(c), c->stream);
   return check_launch(c, "compute forces");
 }
@@ -742,14 +823,14 @@ md_status md_step(md_ctx* c, int32_t n_steps) {
   md_status st;
   for (int32_t k = 0; k < n_steps; ++k) {
     const bool last = k == n_steps - 1;
-    const bool build = next_step_builds(c);
+    const bool forced = next_step_forced(c);
     if (c->use_graph) {
-      const int g = (nl_mode(c) && build ? 2 : 0) + (last ? 1 : 0);
+      const int g = (forced ? 2 : 0) + (last ? 1 : 0);
       if ((st = hip_check(c, hipGraphLaunch(c->exec[g], c->stream), "graph launch"))) return st;
     } else {
-      enqueue_step(c, c->stream, last, build);
+      enqueue_step(c, c->stream, last, forced);
     }
-    advance_build_counter(c, build);
+    advance_build_counter(c, forced);
   }
   launch_finalize(c->v, opts(c), c->stream);
   c->step += n_steps;
@@ -773,29 +854,29 @@ md_status md_step_timed(md_ctx* c, int32_t n_steps, double* ms_out) {
   hipStream_t s = c->stream;
   for (int32_t k = 0; k < n_steps; ++k) {
     const bool last = k == n_steps - 1;
-    const bool build = next_step_builds(c);
+    const bool forced = next_step_forced(c);
+    const bool nl = nl_mode(c);
+    const int32_t* gate = nl ? c->v.nl_flag : nullptr;
     hipEvent_t* e = &ev[(size_t)k * P * 2];
     (void)hipEventRecord(e[0], s);
-    if (build)
-      launch_bin_count(c->v, true, opts(c), c->ffd, fp32, s);
-    else
-      launch_nl_integrate(c->v, opts(c), c->ffd, fp32, s);
+    if (nl) launch_nl_integrate(c->v, opts(c), c->ffd, fp32, forced, s);
+    launch_bin_count(c->v, !nl, opts(c), c->ffd, fp32, s, gate);
     (void)hipEventRecord(e[1], s);
     (void)hipEventRecord(e[2], s);
-    if (build) launch_scan(c->v, s);
+    launch_scan(c->v, s, gate);
     (void)hipEventRecord(e[3], s);
     (void)hipEventRecord(e[4], s);
-    if (build) launch_scatter(c->v, s);
+    launch_scatter(c->v, s, gate);
     (void)hipEventRecord(e[5], s);
     (void)hipEventRecord(e[6], s);
-    if (build) launch_rank_payload(c->v, fp32, s);
+    launch_rank_payload(c->v, fp32, s, gate);
     (void)hipEventRecord(e[7], s);
     (void)hipEventRecord(e[14], s);
-    if (build && nl_mode(c)) launch_nl_build(c->v, c->ffd, fp32, c->lj_kernel, s);
+    if (nl) launch_nl_build(c->v, c->ffd, fp32, c->lj_kernel, s, gate);
     (void)hipEventRecord(e[15], s);
     (void)hipEventRecord(e[8], s);
-    if (nl_mode(c))
-      launch_lj_nl(c->v, c->ffd, fp32, c->lj_kernel, last, build, s);
+    if (nl)
+      launch_lj_nl(c->v, c->ffd, fp32, c->lj_kernel, last, s);
     else
       launch_lj(c->v, c->ffd, fp32, c->lj_kernel, last, s);
     (void)hipEventRecord(e[9], s);
@@ -805,7 +886,7 @@ md_status md_step_timed(md_ctx* c, int32_t n_steps, double* ms_out) {
     (void)hipEventRecord(e[12], s);
     launch_reduce(c->v, last, true, opts(c), s);
     (void)hipEventRecord(e[13], s);
-    advance_build_counter(c, build);
+    advance_build_counter(c, forced);
   }
   launch_finalize(c->v, opts(c), s);
   c->step += n_steps;
@@ -849,11 +930,6 @@ md_status md_energies(md_ctx* c, md_energy* out) {
   if (err & kErrNonFinite) {
     c->failed = true;
     return fail(c, MD_ERR_NONFINITE, "a position became non-finite");
-  }
-  if (err & (kErrNlMoved | kErrNlFull)) {
-    c->failed = true;
-    return fail(c, MD_ERR_NLIST, (err & kErrNlMoved) ? "an atom moved more than half the skin since the list build"
-                                                     : "an atom had more list neighbours than the list holds");
   }
   return MD_OK;
 }
@@ -921,6 +997,33 @@ md_status md_observables(md_ctx* c, const md_obs_config* o, uint64_t* pairs, uin
   return check_launch(c, "observables");
 }
 
+md_status md_ree_reference(md_ctx* c) {
+  if (!c) return MD_ERR_ARG;
+  if (!usable(c)) return MD_ERR_STATE;
+  enqueue_ree(c, true, nullptr);
+  return check_launch(c, "end-to-end reference");
+}
+
+md_status md_ree_acf(md_ctx* c, double* acf) {
+  if (!c || !acf) return MD_ERR_ARG;
+  if (!usable(c)) return MD_ERR_STATE;
+  enqueue_ree(c, false, acf);
+  return check_launch(c, "end-to-end autocorrelation");
+}
+
+md_status md_list_builds(md_ctx* c, int64_t* builds) {
+  if (!c || !builds) return MD_ERR_ARG;
+  if (taken_over(c)) return MD_ERR_STATE;
+  *builds = 0;
+  if (!nl_mode(c)) return MD_OK;
+  md_status st;
+  if ((st = hip_check(c, hipStreamSynchronize(c->stream), "sync"))) return st;
+  unsigned long long n = 0;
+  if ((st = hip_check(c, hipMemcpy(&n, c->v.nl_builds, 8, hipMemcpyDeviceToHost), "read list builds"))) return st;
+  *builds = (int64_t)n;
+  return MD_OK;
+}
+
 md_status md_destroy(md_ctx* c) {
   if (!c) return MD_ERR_ARG;
   (void)hipStreamSynchronize(c->stream);
@@ -939,7 +1042,7 @@ const char* md_status_string(md_status s) {
     case MD_ERR_WORKSPACE: return "workspace too small or misaligned";
     case MD_ERR_HIP: return "HIP runtime error";
     case MD_ERR_STATE: return "context in error state";
-    case MD_ERR_NLIST: return "neighbour list invalid (skin exceeded or list full)";
+    case MD_ERR_NLIST: return "neighbour list invalid (not returned: lists rebuild on displacement)";
   }
   return "unknown status";
 }

@@ -154,13 +154,19 @@ struct Views {
   int32_t* nl_count;     // list length per sorted slot [N] (per-atom lists) or per cell [C]
   double* x_build;       // [3N] wrapped positions at the last build (global order)
   int32_t* slot_of;      // [N] sorted slot of each atom at the last build
-  void* pay_cur;         // [N] payload refreshed every step between builds
+  void* pay_cur;         // [N] the current payload: the build's after a rebuild, refreshed every step
+  int32_t* nl_flag;      // rebuild flag of the current step (raised by the update, cleared by the reduction)
+  unsigned long long* nl_builds;   // list builds since init
   double nl_rl2;         // (rc + skin)^2
   double nl_half_skin2;  // (skin / 2)^2
   uint32_t* obs_part;    // [kObsBlocks * kMaxObsBins] block partials of the observables
+  const void* shift_tab;  // [n_boxes][kShiftSlots] stencil shifts in payload units (int32 x3 mixed, double x3
+                          // FP64): slot code = the offset of stencil code, slot kSentinelCode the sentinel's
+  double* ree0;          // [n_chains * 3] end-to-end vectors at the autocorrelation's reference time
+  double* ree_part;      // [n_chains * 2] per-chain terms of the autocorrelation
 };
 
-enum ErrBits : int32_t { kErrNonFinite = 1, kErrNlMoved = 2, kErrNlFull = 4 };
+enum ErrBits : int32_t { kErrNonFinite = 1 };
 
 constexpr int kBdParts = 8;      // block partials of the bonded kernel
 constexpr int kMaxObsBins = 2048;  // histogram bins of one observable (md.h: MD_OBS_MAX_BINS)
@@ -190,19 +196,22 @@ struct StepOpts {
 // ---- launchers (md_kernels.hip) ----
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 void launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
+// gate (neighbour-list mode): a device flag; when it is non-null and reads 0 the kernel does nothing
 void launch_bin_count(const Views& v, bool kick, const StepOpts& o, const FFDev& ff, bool fp32_force,
-                      hipStream_t s);
-void launch_scan(const Views& v, hipStream_t s);
-void launch_scatter(const Views& v, hipStream_t s);
-void launch_rank_payload(const Views& v, bool fp32, hipStream_t s);
+                      hipStream_t s, const int32_t* gate = nullptr);
+void launch_scan(const Views& v, hipStream_t s, const int32_t* gate = nullptr);
+void launch_scatter(const Views& v, hipStream_t s, const int32_t* gate = nullptr);
+void launch_rank_payload(const Views& v, bool fp32, hipStream_t s, const int32_t* gate = nullptr);
 void launch_bonded(const Views& v, const FFDev& ff, bool fp32, BondedMode mode, bool energy, bool com,
                    double dt, hipStream_t s);
 // update: advance the integrator state (thermostat, pending COM velocity) from the sums
 void launch_reduce(const Views& v, bool energy, bool update, const StepOpts& o, hipStream_t s);
 // applies what is pending (Berendsen factor, COM velocity) to the velocities
 void launch_finalize(const Views& v, const StepOpts& o, hipStream_t s);
-// neighbour-list mode: update + displacement check + payload refresh between builds
-void launch_nl_integrate(const Views& v, const StepOpts& o, const FFDev& ff, bool fp32_force, hipStream_t s);
+// neighbour-list mode: update + displacement check (raises nl_flag past half the skin, or always
+// with force_build) + payload refresh
+void launch_nl_integrate(const Views& v, const StepOpts& o, const FFDev& ff, bool fp32_force, bool force_build,
+                         hipStream_t s);
 
 // ---- launchers (md_obs.hip): Section 5 observables of box b ----
 void launch_obs_pairs(const Views& v, int b, int64_t n_atoms, int chain_len, int excl, double dr, int n_bins,
@@ -211,6 +220,9 @@ void launch_obs_dihedrals(const Views& v, int b, int64_t n_atoms, int chain_len,
                           unsigned long long* out, hipStream_t s);
 void launch_obs_chains(const Views& v, const FFDev& ff, int b, int64_t n_chains, int chain_len, double* out,
                        hipStream_t s);
+// end-to-end autocorrelation of box b: reference = store the current vectors as time zero;
+// otherwise out[b] = sum_c R_c . R_c(0) / sum_c |R_c(0)|^2 (device)
+void launch_ree(const Views& v, int b, int64_t n_chains, int chain_len, bool reference, double* out, hipStream_t s);
 
 constexpr int kTileHomesMixed = 8;   // home atoms per pass of a mixed cell-tile wave
 
@@ -218,14 +230,21 @@ constexpr int kTileHomesMixed = 8;   // home atoms per pass of a mixed cell-tile
 void launch_lj(const Views& v, const FFDev& ff, bool fp32, int kernel, bool energy, hipStream_t s);
 int64_t lj_blocks_for_box(int kernel, int64_t n_atoms, int64_t n_cells);
 // neighbour-list mode: the list build (from the bins) and the LJ force from the list;
-// build_step: the payload of the build is current (else pay_cur is)
+// the force reads the current payload (pay_cur); gate: as for the bin kernels
 // kernel: MD_LJ_NLIST (per-atom lists) or MD_LJ_NLIST_TILE (per-cell lists)
-void launch_nl_build(const Views& v, const FFDev& ff, bool fp32, int kernel, hipStream_t s);
-void launch_lj_nl(const Views& v, const FFDev& ff, bool fp32, int kernel, bool energy, bool build_step,
-                  hipStream_t s);
+void launch_nl_build(const Views& v, const FFDev& ff, bool fp32, int kernel, hipStream_t s,
+                     const int32_t* gate = nullptr);
+void launch_lj_nl(const Views& v, const FFDev& ff, bool fp32, int kernel, bool energy, hipStream_t s);
 constexpr int kLjNlBlock = 256;   // threads per block of the list force kernel (box-aligned)
 constexpr int kTileWaves = 1;     // home cells (wavefronts) per block of the cell-tile kernels
 constexpr int kXcds = 8;          // accelerator complex dies of an MI355X (one L2 each)
 constexpr int kTileMaxR = 2;      // stencil radii the cell-tile kernel supports
+// Stencil shift table (R <= 2: at most 125 codes).  The last slot shifts a candidate by R + 1
+// cell edges in x and in y: the candidate list is padded to whole 64-lane steps with entries
+// sorted index 0 | kSentinelCode, which then lie at least sqrt(2) R edges >= sqrt(2) rc from
+// every home atom, so they never count and need no bounds test.
+constexpr int kShiftSlots = 128;
+constexpr int kSentinelCode = kShiftSlots - 1;
+constexpr uint32_t kSentinelEntry = (uint32_t)kSentinelCode;
 
 }  // namespace mdk

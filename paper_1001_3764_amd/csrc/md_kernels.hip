@@ -93,7 +93,8 @@ __device__ inline int aggregated_slot(int32_t* cnt, int c, bool active) {
 // kdt: dt / 2 (velocity Verlet half kick) or dt (leap-frog)
 template <typename F, bool KICK>
 __global__ __launch_bounds__(kAtomBlock) void k_bin_count(Views v, const F* __restrict__ f, double dt,
-                                                        double kdt, FFDev ff) {
+                                                        double kdt, FFDev ff, const int32_t* __restrict__ gate) {
+  if (gate && *gate == 0) return;   // neighbour-list mode: no rebuild this step
   const int b = v.blk_box[blockIdx.x];
   const BoxDev B = v.boxes[b];   // read at entry, before any store: scalar loads
   const int local = ((int)blockIdx.x - B.blk_off) * kAtomBlock + (int)threadIdx.x;
@@ -171,7 +172,8 @@ __device__ T block_exclusive_scan(T val, T* sh, T* total) {
 }
 
 __global__ __launch_bounds__(kScanBlock) void k_scan_tiles(const int32_t* __restrict__ cnt, int64_t C,
-                                                          int32_t* tiles) {
+                                                          int32_t* tiles, const int32_t* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   __shared__ int sh[33];
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
   int s = 0;
@@ -190,7 +192,9 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_tiles(const int32_t* __rest
 template <bool ONE>
 __global__ __launch_bounds__(kScanBlock) void k_scan(int32_t* __restrict__ cnt, int64_t C,
                                                     const int32_t* __restrict__ tiles,
-                                                    int32_t* __restrict__ cell_start) {
+                                                    int32_t* __restrict__ cell_start,
+                                                    const int32_t* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   __shared__ long long sh[33];
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
   int vals[kScanItems];
@@ -227,7 +231,8 @@ __global__ __launch_bounds__(kScanBlock) void k_scan(int32_t* __restrict__ cnt, 
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) cell_start[C] = offset + total;
 }
 
-__global__ __launch_bounds__(kAtomBlock) void k_scatter(Views v) {
+__global__ __launch_bounds__(kAtomBlock) void k_scatter(Views v, const int32_t* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   const int b = v.blk_box[blockIdx.x];
   const BoxDev B = v.boxes[b];   // read at entry, before any store: scalar loads
   const int local = ((int)blockIdx.x - B.blk_off) * kAtomBlock + (int)threadIdx.x;
@@ -266,7 +271,8 @@ __device__ inline void store_payload<Pay64>(Pay64* p, int64_t dst, double rx, do
 constexpr int kRankBatch = 4;   // list entries read together by the rank walk
 
 template <typename PayT>
-__global__ __launch_bounds__(kAtomBlock) void k_rank_payload(Views v) {
+__global__ __launch_bounds__(kAtomBlock) void k_rank_payload(Views v, const int32_t* __restrict__ gate) {
+  if (gate && *gate == 0) return;
   const int b = v.blk_box[blockIdx.x];
   const BoxDev B = v.boxes[b];   // read at entry, before any store: scalar loads
   const int local = ((int)blockIdx.x - B.blk_off) * kAtomBlock + (int)threadIdx.x;
@@ -301,7 +307,8 @@ __global__ __launch_bounds__(kAtomBlock) void k_rank_payload(Views v) {
   const double rz = z - ((double)kz + 0.5) * B.edge[2];
   const int32_t tag = (i << 4) | ((ty & 1) << 3) | (kx & 7);
   store_payload<PayT>(static_cast<PayT*>(v.payload), dst, rx, ry, rz, tag);
-  if (v.nl_cap) {   // neighbour-list mode: where the list build saw the atom
+  if (v.nl_cap) {   // neighbour-list mode: where the list build saw the atom; the current payload
+    store_payload<PayT>(static_cast<PayT*>(v.pay_cur), dst, rx, ry, rz, tag);   // is the build's
     v.slot_of[i] = dst;
     v.x_build[i] = x;
     v.x_build[N + i] = y;
@@ -332,15 +339,18 @@ __device__ inline void refresh_payload<Pay64>(const Pay64* build, Pay64* cur, in
 }
 
 // Velocity update, drift and wrap as in k_bin_count, without binning; then
-// the displacement since the list build (flagged when above half the skin) moves the
-// atom's build payload to its current place: cur = build + round(d * 2^25) (mixed) or
-// build + d (FP64), so pair differences stay exact integers in the mixed form.
+// the displacement since the list build moves the atom's build payload to its current place:
+// cur = build + round(d * 2^25) (mixed) or build + d (FP64), so pair differences stay exact
+// integers in the mixed form.  A displacement above half the skin (or force) raises the
+// rebuild flag: this step's gated bin and list kernels then rebuild from the new positions
+// before the forces are evaluated, so the list in use always holds every pair within rc.
 template <typename F, typename PayT>
 __global__ __launch_bounds__(kAtomBlock) void k_nl_integrate(Views v, const F* __restrict__ f, double dt,
-                                                          double kdt, FFDev ff) {
+                                                          double kdt, FFDev ff, int force) {
   const int b = v.blk_box[blockIdx.x];
   const BoxDev B = v.boxes[b];   // read at entry, before any store: scalar loads
   const int local = ((int)blockIdx.x - B.blk_off) * kAtomBlock + (int)threadIdx.x;
+  if (force && blockIdx.x == 0 && threadIdx.x == 0) *v.nl_flag = 1;
   if (local >= B.n_atoms) return;
   const int64_t N = v.N;
   const int64_t i = (int64_t)B.atom_off + local;
@@ -366,7 +376,8 @@ __global__ __launch_bounds__(kAtomBlock) void k_nl_integrate(Views v, const F* _
   const double dx = min_image(x - v.x_build[i], B.L[0], B.invL[0]);
   const double dy = min_image(y - v.x_build[N + i], B.L[1], B.invL[1]);
   const double dz = min_image(z - v.x_build[2 * N + i], B.L[2], B.invL[2]);
-  if (dx * dx + dy * dy + dz * dz > v.nl_half_skin2) atomicOr(v.err, (int)kErrNlMoved);
+  const bool moved = dx * dx + dy * dy + dz * dz > v.nl_half_skin2;
+  if (__builtin_amdgcn_ballot_w64(moved) != 0 && lane() == 0) *v.nl_flag = 1;   // same value from every writer
   refresh_payload<PayT>(static_cast<const PayT*>(v.payload), static_cast<PayT*>(v.pay_cur), v.slot_of[i], dx, dy,
                         dz);
 }
@@ -650,12 +661,18 @@ __device__ void block_sums(dd (&s)[NV], dd (*sh)[NV]) {
 //              KE - |P|^2 / (2 M).
 // Bonded partials: 0 E_b, 1 E_a, 2 E_d, 3 W_b, 4 KE, 5..7 momentum; LJ: E, E_shifted, W.
 // ENERGY: the energies and virial too; COM (with update): the momentum and u.
+// Neighbour-list mode, with update: the step's rebuild flag has been read by every kernel
+// that uses it, so it is counted and cleared here for the next step.
 template <bool ENERGY, bool COM>
 __global__ __launch_bounds__(256) void k_reduce(Views v, int update, StepOpts o) {
   // q: KE, [momentum xyz], [E_b E_a E_d W_b E_lj E_lj_shifted W_lj]
   constexpr int iP = 1, iE = COM ? 4 : 1, NV = iE + (ENERGY ? 7 : 0);
   __shared__ dd sh[4][NV];
   const int b = blockIdx.x;
+  if (update && v.nl_flag && b == 0 && threadIdx.x == 0 && *v.nl_flag) {
+    *v.nl_builds += 1ull;
+    *v.nl_flag = 0;
+  }
   const BoxDev B = v.boxes[b];   // read at entry, before any store: scalar loads
   const int first = B.blk_off;
   const int count = (B.n_atoms + kAtomBlock - 1) / kAtomBlock;
@@ -793,38 +810,38 @@ void launch_fill_f64(double* p, int64_t n, double v, hipStream_t s) {
 static double kick_dt(const StepOpts& o) { return o.integrator == kLeapfrogNoseHoover ? o.dt : 0.5 * o.dt; }
 
 void launch_bin_count(const Views& v, bool kick, const StepOpts& o, const FFDev& ff, bool fp32_force,
-                      hipStream_t s) {
+                      hipStream_t s, const int32_t* gate) {
   dim3 g(v.n_atom_blocks), blk(kAtomBlock);
   const double kdt = kick_dt(o);
   if (!kick)
-    hipLaunchKernelGGL((k_bin_count<float, false>), g, blk, 0, s, v, (const float*)nullptr, o.dt, kdt, ff);
+    hipLaunchKernelGGL((k_bin_count<float, false>), g, blk, 0, s, v, (const float*)nullptr, o.dt, kdt, ff, gate);
   else if (fp32_force)
-    hipLaunchKernelGGL((k_bin_count<float, true>), g, blk, 0, s, v, (const float*)v.f_tot, o.dt, kdt, ff);
+    hipLaunchKernelGGL((k_bin_count<float, true>), g, blk, 0, s, v, (const float*)v.f_tot, o.dt, kdt, ff, gate);
   else
-    hipLaunchKernelGGL((k_bin_count<double, true>), g, blk, 0, s, v, (const double*)v.f_tot, o.dt, kdt, ff);
+    hipLaunchKernelGGL((k_bin_count<double, true>), g, blk, 0, s, v, (const double*)v.f_tot, o.dt, kdt, ff, gate);
 }
 
 static int scan_tiles(const Views& v) { return (int)((v.C + kScanTile - 1) / kScanTile); }
 
-void launch_scan(const Views& v, hipStream_t s) {
+void launch_scan(const Views& v, hipStream_t s, const int32_t* gate) {
   const int n = scan_tiles(v);
   if (n <= kScanOnePass) {
-    hipLaunchKernelGGL(k_scan<true>, dim3(n), dim3(kScanBlock), 0, s, v.cnt, v.C, v.scan_tiles, v.cell_start);
+    hipLaunchKernelGGL(k_scan<true>, dim3(n), dim3(kScanBlock), 0, s, v.cnt, v.C, v.scan_tiles, v.cell_start, gate);
     return;
   }
-  hipLaunchKernelGGL(k_scan_tiles, dim3(n), dim3(kScanBlock), 0, s, v.cnt, v.C, v.scan_tiles);
-  hipLaunchKernelGGL(k_scan<false>, dim3(n), dim3(kScanBlock), 0, s, v.cnt, v.C, v.scan_tiles, v.cell_start);
+  hipLaunchKernelGGL(k_scan_tiles, dim3(n), dim3(kScanBlock), 0, s, v.cnt, v.C, v.scan_tiles, gate);
+  hipLaunchKernelGGL(k_scan<false>, dim3(n), dim3(kScanBlock), 0, s, v.cnt, v.C, v.scan_tiles, v.cell_start, gate);
 }
 
-void launch_scatter(const Views& v, hipStream_t s) {
-  hipLaunchKernelGGL(k_scatter, dim3(v.n_atom_blocks), dim3(kAtomBlock), 0, s, v);
+void launch_scatter(const Views& v, hipStream_t s, const int32_t* gate) {
+  hipLaunchKernelGGL(k_scatter, dim3(v.n_atom_blocks), dim3(kAtomBlock), 0, s, v, gate);
 }
 
-void launch_rank_payload(const Views& v, bool fp32, hipStream_t s) {
+void launch_rank_payload(const Views& v, bool fp32, hipStream_t s, const int32_t* gate) {
   if (fp32)
-    hipLaunchKernelGGL(k_rank_payload<int4>, dim3(v.n_atom_blocks), dim3(kAtomBlock), 0, s, v);
+    hipLaunchKernelGGL(k_rank_payload<int4>, dim3(v.n_atom_blocks), dim3(kAtomBlock), 0, s, v, gate);
   else
-    hipLaunchKernelGGL(k_rank_payload<Pay64>, dim3(v.n_atom_blocks), dim3(kAtomBlock), 0, s, v);
+    hipLaunchKernelGGL(k_rank_payload<Pay64>, dim3(v.n_atom_blocks), dim3(kAtomBlock), 0, s, v, gate);
 }
 
 template <typename P>
@@ -864,13 +881,15 @@ void launch_reduce(const Views& v, bool energy, bool update, const StepOpts& o, 
   }
 }
 
-void launch_nl_integrate(const Views& v, const StepOpts& o, const FFDev& ff, bool fp32_force, hipStream_t s) {
+void launch_nl_integrate(const Views& v, const StepOpts& o, const FFDev& ff, bool fp32_force, bool force_build,
+                         hipStream_t s) {
   dim3 g(v.n_atom_blocks), blk(kAtomBlock);
   const double kdt = kick_dt(o);
+  const int fb = force_build ? 1 : 0;
   if (fp32_force)
-    hipLaunchKernelGGL((k_nl_integrate<float, int4>), g, blk, 0, s, v, (const float*)v.f_tot, o.dt, kdt, ff);
+    hipLaunchKernelGGL((k_nl_integrate<float, int4>), g, blk, 0, s, v, (const float*)v.f_tot, o.dt, kdt, ff, fb);
   else
-    hipLaunchKernelGGL((k_nl_integrate<double, Pay64>), g, blk, 0, s, v, (const double*)v.f_tot, o.dt, kdt, ff);
+    hipLaunchKernelGGL((k_nl_integrate<double, Pay64>), g, blk, 0, s, v, (const double*)v.f_tot, o.dt, kdt, ff, fb);
 }
 
 void launch_finalize(const Views& v, const StepOpts& o, hipStream_t s) {

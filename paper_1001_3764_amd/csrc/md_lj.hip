@@ -23,6 +23,8 @@
 //   k_nl_build,      neighbour-list builds (Sections 3.1-3.2), per atom and per cell, and
 //   k_nl_build_tile, the per-atom list walk.
 //   k_lj_nl
+#include <algorithm>
+#include <cmath>
 #include <type_traits>
 
 #include "md_internal.h"
@@ -166,6 +168,9 @@ __device__ __forceinline__ T group_sum(T x, int from) {
 // Relative half-width of the band around rc^2 decided in FP64 (well above the FP32 error
 // of r^2 from exact fixed-point differences, ~3e-7, plus the 2^-26 A position rounding).
 constexpr double kBand = 1e-6;
+// Close contacts (r < kCloseSigma sigma, where the pair force exceeds ~50 kcal/mol/A for the
+// polyethylene parameters) are evaluated in FP64 (see Band).
+constexpr double kCloseSigma = 0.75;
 constexpr int kBandQueue = 64;   // band pairs a tile wave queues per home group
 constexpr int kBandSteps = 8;    // candidate steps with band pairs a tile wave records per group
 
@@ -182,7 +187,8 @@ template <typename P>
 struct LjPair {
   P f12[4], f6[4], e12[4], e6[4], ecut[4];
   P f12_fold;               // f12[0] / f6[0] (one type pair: the force factor's inline constant)
-  float band_lo, band_hi;   // the cutoff band of make_band, computed once on the host
+  float band_lo, band_hi;   // the cutoff band (see Band), computed once on the host
+  float close;              // close-contact bound (see Band), computed once on the host
 };
 
 template <typename P>
@@ -190,19 +196,27 @@ __device__ inline P pick(const P* a, int t) {
   return t == 0 ? a[0] : (t == 1 ? a[1] : (t == 2 ? a[2] : a[3]));
 }
 
-// Cutoff band, in the fixed-point units of r2s (2^-50 A^2).  The FP32 path counts a pair
-// as inside when r2s < hi.  Pairs with lo <= r2s < hi are in the band: there the FP32
-// r^2 cannot tell the side of the cutoff, so each is re-decided in FP64 and, if the FP64
-// test puts it outside, its force is taken back out (remove_band_pair).
+// The two ends of the FP32 pair range, in the fixed-point units of r2s (2^-50 A^2).
+// Cutoff band: the FP32 path counts a pair as inside when r2s < hi.  Pairs with
+// lo <= r2s < hi are in the band: there the FP32 r^2 cannot tell the side of the cutoff, so
+// each is re-decided in FP64 and, if the FP64 test puts it outside, its force is taken back
+// out (remove_band_pair).
+// Close contacts: pairs with r2s < close (r below kCloseSigma times the smallest LJ sigma)
+// never enter the FP32 sums.  Their force grows as r^-13 and FP32's few-ulp relative error
+// on it would exceed 1e-5 of the RMS force (a contact at 2.0 A in a grown melt carries
+// ~80 times the RMS force); each is evaluated in FP64 from the FP64 positions instead and
+// added to its home's force (add_close_pair).  They are rare in a melt.
 struct Band {
-  float lo, hi;
+  float lo, hi, close;
 };
-__device__ inline Band make_band(double rc2) {
-  return Band{(float)(rc2 * kFix * kFix * (1.0 - kBand)), (float)(rc2 * kFix * kFix * (1.0 + kBand))};
+template <typename P>
+__device__ inline Band band_of(const LjPair<P>& c) {
+  return Band{c.band_lo, c.band_hi, c.close};
 }
 __device__ __forceinline__ bool in_band(float r2s, bool keep, const Band& b) {
   return keep && r2s >= b.lo && r2s < b.hi;
 }
+__device__ __forceinline__ bool is_close(float r2s, bool keep, const Band& b) { return keep && r2s < b.close; }
 
 // Exact cutoff test for a band pair (about one candidate in 10^6): r^2 < rc^2 decided from
 // the FP64 positions with the operation order of a plain FP64 evaluation (no fused
@@ -242,6 +256,27 @@ __device__ __forceinline__ void remove_band_pair(const double (&d)[3], double r2
   }
 }
 
+// Adds a close contact to FP64 accumulators (kcal/mol/A): the force from the FP64
+// minimum-image difference d = x_i - x_j, in a plain FP64 operation order.
+template <bool ENERGY>
+__device__ __forceinline__ void add_close_pair(const double (&d)[3], double r2, double f12, double f6, double e12,
+                                               double e6, double ecut, double& cx, double& cy, double& cz,
+                                               double& e, double& es, double& w) {
+  const double r2i = 1.0 / r2;
+  const double r6 = r2i * r2i * r2i;
+  const double g = r6 * (f12 * r6 - f6);
+  const double ffs = g * r2i;
+  cx += ffs * d[0];
+  cy += ffs * d[1];
+  cz += ffs * d[2];
+  if (ENERGY) {
+    const double en = r6 * (e12 * r6 - e6);
+    e += en;
+    es += en - ecut;
+    w += g;
+  }
+}
+
 // x clamped to [lo, hi] (lo <= hi), for the bounding-box filter.  Fixed point: the median
 // of the three in one instruction (the compiler cannot prove lo <= hi, and a max and a min
 // are two); FP64: a max and a min.
@@ -262,17 +297,22 @@ __device__ __forceinline__ float r2_fix(float dx, float dy, float dz) {
 // accumulated in a* is in units of 2^25 (the caller scales the final sum by 2^-25).
 // Pairs in the cutoff band are counted; bmax keeps the bits of the largest r2s counted
 // (r2s >= 0, so integer order is float order), so that the caller sees a band pair
-// (bmax >= lo) at one integer max per pair and settles it.
+// (bmax >= lo) at one integer max per pair and settles it.  A close contact (r2s < close)
+// is not counted: near is set, and the caller evaluates it in FP64.
 // Returns r2s.  BRANCHLESS evaluates the force for every lane and zeroes it outside.
 // FOLD: f12 holds f12 / f6 and the caller multiplies the summed force by f6 (one type
 // pair: the force factor is then one FMA with an inline constant and no register copy).
 template <bool ENERGY, bool BRANCHLESS, bool FOLD = false>
 __device__ __forceinline__ float pair_fix(int dqx, int dqy, int dqz, bool keep, const Band& bd, float f12,
                                           float f6, float e12, float e6, float ecut, float& ax, float& ay,
-                                          float& az, double& e, double& es, double& w, int32_t& bmax) {
+                                          float& az, double& e, double& es, double& w, int32_t& bmax,
+                                          bool& near) {
   const float dx = (float)dqx, dy = (float)dqy, dz = (float)dqz;
   const float r2s = r2_fix(dx, dy, dz);
-  const bool hit = keep && r2s < bd.hi;
+  const bool lt_close = r2s < bd.close;   // one compare serves both masks
+  const bool kh = keep && r2s < bd.hi;
+  near = near || (kh && lt_close);
+  const bool hit = kh && !lt_close;
   if (BRANCHLESS || hit) {
     const float r2 = r2s * kInvFix2F;
     const float r2i = rcp_f(r2);
@@ -350,7 +390,7 @@ __global__ __launch_bounds__(kLjAtomBlock) void k_lj_atom(Views v, FFDev ff, LjP
   const PayT* __restrict__ pay = static_cast<const PayT*>(v.payload);
   const int32_t* __restrict__ cstart = v.cell_start;
   const int R = v.R;
-  const Band bd = make_band(ff.rc2);
+  const Band bd = band_of(cf);
   double e = 0.0, es = 0.0, w = 0.0;
   if (active) {
     const int64_t s = (int64_t)B.atom_off + local;
@@ -367,6 +407,7 @@ __global__ __launch_bounds__(kLjAtomBlock) void k_lj_atom(Views v, FFDev ff, LjP
     const Cell3 k3 = cell_coords(c, B);
     const int kx = k3.x, ky = k3.y, kz = k3.z;
     P fx = 0, fy = 0, fz = 0;
+    double cx = 0.0, cy = 0.0, cz = 0.0;   // close contacts (mixed), FP64
     for (int oz = -R; oz <= R; ++oz) {
       int nz = kz + oz;
       nz += nz < 0 ? M2 : 0;
@@ -400,22 +441,28 @@ __global__ __launch_bounds__(kLjAtomBlock) void k_lj_atom(Views v, FFDev ff, LjP
               const bool keep = (uint32_t)(tag_index(tj) - lo) > span;
               const int tt = ff.uniform_lj ? 0 : ti * 2 + tag_type(tj);
               int32_t bmax = 0;
+              bool near = false;
               const float r2s = pair_fix<ENERGY, false>(hx - pj.x, hy - pj.y, hz - pj.z, keep, bd, pick(cf.f12, tt),
                                                         pick(cf.f6, tt), pick(cf.e12, tt), pick(cf.e6, tt),
-                                                        pick(cf.ecut, tt), fx, fy, fz, e, es, w, bmax);
+                                                        pick(cf.ecut, tt), fx, fy, fz, e, es, w, bmax, near);
               double d[3], r2;
               if (in_band(r2s, keep, bd) && !inside_cutoff_f64(v.pos, v.N, B, i, tag_index(tj), ff.rc2, d, r2))
                 remove_band_pair<ENERGY>(d, r2, pick(cf.f12, tt), pick(cf.f6, tt), pick(cf.e12, tt),
                                          pick(cf.e6, tt), pick(cf.ecut, tt), fx, fy, fz, e, es, w);
+              if (near) {   // rare: a close contact, in FP64
+                inside_cutoff_f64(v.pos, v.N, B, i, tag_index(tj), ff.rc2, d, r2);
+                add_close_pair<ENERGY>(d, r2, pick(cd.f12, tt), pick(cd.f6, tt), pick(cd.e12, tt), pick(cd.e6, tt),
+                                       pick(cd.ecut, tt), cx, cy, cz, e, es, w);
+              }
             }
           }
         }
       }
     }
     if constexpr (!FP64) {
-      fx *= kInvFixF;
-      fy *= kInvFixF;
-      fz *= kInvFixF;
+      fx = (float)((double)fx * (double)kInvFixF + cx);
+      fy = (float)((double)fy * (double)kInvFixF + cy);
+      fz = (float)((double)fz * (double)kInvFixF + cz);
     }
     P* f = static_cast<P*>(v.f_lj);
     f[i] = fx;
@@ -440,6 +487,13 @@ template <typename Q>
 struct Shift {
   Q x, y, z;   // stencil offset (ox, oy, oz) times the cell edge, in the payload's units
 };
+
+// Box b's stencil shift table (kShiftSlots entries, built on the host) into LDS.
+template <typename Q>
+__device__ __forceinline__ void load_shifts(const Views& v, int b, Shift<Q>* shifts) {
+  const Shift<Q>* __restrict__ tab = static_cast<const Shift<Q>*>(v.shift_tab) + (int64_t)b * kShiftSlots;
+  for (int c = (int)threadIdx.x; c < kShiftSlots; c += (int)blockDim.x) shifts[c] = tab[c];
+}
 
 // Exclusive prefix sum of x >= 0 over the wave, bit plane by bit plane: the lanes below
 // this one whose bit b is set add 2^b each (a ballot and a masked popcount per plane).
@@ -497,42 +551,54 @@ __device__ __forceinline__ int fill_list(const Views& v, const BoxDev& B, int lc
 // The candidate list of home cell lc, entries [c0, c0 + kListCap), into list[]; returns its
 // full length.  Cell path: the whole stencil, listed here.  Neighbour-list mode with cell
 // lists (LIST): the cell's own list, the candidates within rc + skin of any of its atoms at
-// the last build (k_nl_build_tile), copied from HBM.
+// the last build (k_nl_build_tile), copied from HBM; a cell whose list outgrew its capacity
+// streams its whole stencil instead (the bins of the build: every atom has moved less than
+// half the skin since, and the stencil covers rc + skin, so every pair within rc is in it).
+// The chunk is padded with the sentinel entry from its end up to and including the next
+// multiple of 64 (list holds kListCap + 65 entries).
 template <bool LIST>
 __device__ __forceinline__ int load_list(const Views& v, const BoxDev& B, int lc, int c0, uint32_t* list) {
+  int n;
   if constexpr (!LIST) {
-    return fill_list(v, B, lc, c0, list);
+    n = fill_list(v, B, lc, c0, list);
   } else {
-    const int n = v.nl_count[B.cell_off + lc];
-    const uint32_t* __restrict__ src = v.nl_list + B.nl_off + (int64_t)lc * v.nl_cap;
-    const int m = min(kListCap, n - c0);
-    for (int t = lane(); t < m; t += 64) list[t] = src[c0 + t];
-    return n;
+    n = v.nl_count[B.cell_off + lc];
+    if (n > v.nl_cap) {
+      n = fill_list(v, B, lc, c0, list);
+    } else {
+      const uint32_t* __restrict__ src = v.nl_list + B.nl_off + (int64_t)lc * v.nl_cap;
+      const int m = min(kListCap, n - c0);
+      for (int t = lane(); t < m; t += 64) list[t] = src[c0 + t];
+    }
   }
+  const int cn = min(kListCap, n - c0);
+  if (lane() <= ((cn + 63) & ~63) - cn) list[cn + lane()] = kSentinelEntry;
+  return n;
 }
 
 struct BandEnergy {
   double e, es, w;
 };
 
-// Settles the cutoff-band pairs of one home group of a mixed tile wave, after its home
-// forces are stored.  The recorded candidate steps (flat list positions) are revisited and
-// their band pairs queued in (step, home, lane) order, refilling the list where a step lies
-// in another chunk; each queued pair is then re-decided in FP64 and, when outside, taken
-// back out of the stored force of its home (summed per home over the lanes, applied by the
-// lane that stored that home: lane k << SHIFT for home k).  With more steps or pairs than
-// the slots hold (not expected in a melt) every candidate of the group is walked again
-// instead, from the full list (total entries).  LDS executes a wave's accesses in order
-// and only this wave wrote its slots, so no barrier is needed.  `resident` is the chunk
+// Settles the cutoff-band pairs and the close contacts of one home group of a mixed tile wave,
+// after its home forces are stored.  The recorded candidate steps (flat list positions) are
+// revisited and their band pairs and close contacts queued in (step, home, lane) order,
+// refilling the list where a step lies in another chunk.  Each queued band pair is re-decided
+// in FP64 and, when outside, its FP32 force is taken back out; each close contact is evaluated
+// in FP64 and added.  Both are summed per home over the lanes in a fixed order and applied in
+// one rounding by the lane that stored that home (lane k << SHIFT for home k).  With more
+// steps or pairs than the slots hold (not expected in a melt) every candidate of the group is
+// walked again instead, from the full list (total entries).  LDS executes a wave's accesses in
+// order and only this wave wrote its slots, so no barrier is needed.  `resident` is the chunk
 // the list holds, or kCompacted when it holds the group's ncand filtered candidates (the
 // positions the steps were recorded at); it is updated.
 template <bool ENERGY, bool UNI, bool LIST, int SHIFT>
-__device__ __forceinline__ BandEnergy settle_band_group(const Views& v, int chain_len, int excl, double rc2,
-                                                        const LjPair<float>& cf, const BoxDev& B, Band bd, int lc,
-                                                        int total, int ncand, uint32_t* list, int& resident,
-                                                        const Shift<int>* shifts, const int* steps, int32_t* bq,
-                                                        const int4* __restrict__ pay, int hs, int g0, int kc,
-                                                        int nsteps) {
+__device__ __forceinline__ BandEnergy settle_group(const Views& v, int chain_len, int excl, double rc2,
+                                                   const LjPair<float>& cf, const LjPair<double>& cd,
+                                                   const BoxDev& B, Band bd, int lc, int total, int ncand,
+                                                   uint32_t* list, int& resident, const Shift<int>* shifts,
+                                                   const int* steps, int32_t* bq, const int4* __restrict__ pay,
+                                                   int hs, int g0, int kc, int nsteps) {
   const int ln = lane();
   float* f = static_cast<float*>(v.f_lj);
   double e = 0.0, es = 0.0, w = 0.0;
@@ -555,7 +621,34 @@ __device__ __forceinline__ BandEnergy settle_band_group(const Views& v, int chai
     hlo = max(i - excl, c0);
     hspan = (uint32_t)(min(i + excl, c0 + chain_len - 1) - hlo);
   };
-  int qn = 0;
+  // one queued pair's correction on this lane: band (FP32, units of 2^25) or close (FP64)
+  auto correct = [&](int32_t i, int32_t j, int tt, bool close, float& bx, float& by, float& bz, double& cx,
+                     double& cy, double& cz) {
+    double d[3], r2;
+    const bool inside = inside_cutoff_f64(v.pos, v.N, B, i, j, rc2, d, r2);
+    if (close)
+      add_close_pair<ENERGY>(d, r2, pick(cd.f12, tt), pick(cd.f6, tt), pick(cd.e12, tt), pick(cd.e6, tt),
+                             pick(cd.ecut, tt), cx, cy, cz, e, es, w);
+    else if (!inside)
+      remove_band_pair<ENERGY>(d, r2, pick(cf.f12, tt), pick(cf.f6, tt), pick(cf.e12, tt), pick(cf.e6, tt),
+                               pick(cf.ecut, tt), bx, by, bz, e, es, w);
+  };
+  // home k's corrections summed over the lanes, added to its stored force in one rounding
+  auto apply = [&](int k, float bx, float by, float bz, double cx, double cy, double cz) {
+    bx = group_sum(bx, 0);
+    by = group_sum(by, 0);
+    bz = group_sum(bz, 0);
+    cx = group_sum(cx, 0);
+    cy = group_sum(cy, 0);
+    cz = group_sum(cz, 0);
+    if (ln == k << SHIFT) {
+      const int32_t i = tag_index(pay_tag(pay[hs + g0 + k]));
+      f[i] = (float)((double)f[i] + ((double)(bx * kInvFixF) + cx));
+      f[v.N + i] = (float)((double)f[v.N + i] + ((double)(by * kInvFixF) + cy));
+      f[2 * v.N + i] = (float)((double)f[2 * v.N + i] + ((double)(bz * kInvFixF) + cz));
+    }
+  };
+  int qn = 0;   // queued pairs: j << 6 | type_j << 5 | close << 4 | k
   if (nsteps <= kBandSteps) {
     for (int s = 0; s < nsteps; ++s) {
       const int fs = steps[s];
@@ -573,40 +666,32 @@ __device__ __forceinline__ BandEnergy settle_band_group(const Views& v, int chai
         uint32_t hspan;
         window(tag_index(pay_tag(hq)), hlo, hspan);
         const bool keep = act && (uint32_t)(tag_index(jt) - hlo) > hspan;
-        const bool qb = in_band(r2_fix((float)(hq.x - jx), (float)(hq.y - jy), (float)(hq.z - jz)), keep, bd);
+        const float r2s = r2_fix((float)(hq.x - jx), (float)(hq.y - jy), (float)(hq.z - jz));
+        const bool qc = is_close(r2s, keep, bd);
+        const bool qb = qc || in_band(r2s, keep, bd);
         const uint64_t qm = __builtin_amdgcn_ballot_w64(qb);
         const int at = qn + lanes_below(qm);
-        if (qb && at < kBandQueue) bq[at] = (tag_index(jt) << 4) | (tag_type(jt) << 3) | k;
+        if (qb && at < kBandQueue) bq[at] = (tag_index(jt) << 6) | (tag_type(jt) << 5) | ((int)qc << 4) | k;
         qn += __popcll(qm);
       }
     }
   }
   if (nsteps <= kBandSteps && qn <= kBandQueue) {
     float bx = 0.0f, by = 0.0f, bz = 0.0f;
+    double cx = 0.0, cy = 0.0, cz = 0.0;
     int kq = -1;
     if (ln < qn) {
       const int32_t ent = bq[ln];
-      const int32_t htag = pay_tag(pay[hs + g0 + (ent & 7)]);
-      double d[3], r2;
-      if (!inside_cutoff_f64(v.pos, v.N, B, tag_index(htag), ent >> 4, rc2, d, r2)) {
-        const int tt = UNI ? 0 : tag_type(htag) * 2 + ((ent >> 3) & 1);
-        remove_band_pair<ENERGY>(d, r2, pick(cf.f12, tt), pick(cf.f6, tt), pick(cf.e12, tt), pick(cf.e6, tt),
-                                 pick(cf.ecut, tt), bx, by, bz, e, es, w);
-        kq = ent & 7;
-      }
+      kq = ent & 15;
+      const int32_t htag = pay_tag(pay[hs + g0 + kq]);
+      const int tt = UNI ? 0 : tag_type(htag) * 2 + ((ent >> 5) & 1);
+      correct(tag_index(htag), ent >> 6, tt, ((ent >> 4) & 1) != 0, bx, by, bz, cx, cy, cz);
     }
     for (int k = 0; k < kc; ++k) {
       if (__builtin_amdgcn_ballot_w64(kq == k) == 0) continue;
-      float sx = kq == k ? bx : 0.0f, sy = kq == k ? by : 0.0f, sz = kq == k ? bz : 0.0f;
-      sx = group_sum(sx, 0);
-      sy = group_sum(sy, 0);
-      sz = group_sum(sz, 0);
-      if (ln == k << SHIFT) {
-        const int32_t i = tag_index(pay_tag(pay[hs + g0 + k]));
-        f[i] += sx * kInvFixF;
-        f[v.N + i] += sy * kInvFixF;
-        f[2 * v.N + i] += sz * kInvFixF;
-      }
+      const bool mine = kq == k;
+      apply(k, mine ? bx : 0.0f, mine ? by : 0.0f, mine ? bz : 0.0f, mine ? cx : 0.0, mine ? cy : 0.0,
+            mine ? cz : 0.0);
     }
   } else {
     for (int k = 0; k < kc; ++k) {
@@ -616,6 +701,7 @@ __device__ __forceinline__ BandEnergy settle_band_group(const Views& v, int chai
       uint32_t hspan;
       window(i, hlo, hspan);
       float bx = 0.0f, by = 0.0f, bz = 0.0f;
+      double cx = 0.0, cy = 0.0, cz = 0.0;
       for (int c0 = 0; c0 < total; c0 += kListCap) {
         if (c0 != resident) {
           load_list<LIST>(v, B, lc, c0, list);
@@ -627,24 +713,14 @@ __device__ __forceinline__ BandEnergy settle_band_group(const Views& v, int chai
           int32_t jt;
           const bool act = candidate(t0 + ln, cn, jx, jy, jz, jt);
           const int32_t jidx = tag_index(jt);
+          const bool keep = act && (uint32_t)(jidx - hlo) > hspan;
           const float r2s = r2_fix((float)(hq.x - jx), (float)(hq.y - jy), (float)(hq.z - jz));
-          double d[3], r2;
-          if (in_band(r2s, act && (uint32_t)(jidx - hlo) > hspan, bd) &&
-              !inside_cutoff_f64(v.pos, v.N, B, i, jidx, rc2, d, r2)) {
-            const int tt = UNI ? 0 : tag_type(pay_tag(hq)) * 2 + tag_type(jt);
-            remove_band_pair<ENERGY>(d, r2, pick(cf.f12, tt), pick(cf.f6, tt), pick(cf.e12, tt),
-                                     pick(cf.e6, tt), pick(cf.ecut, tt), bx, by, bz, e, es, w);
-          }
+          const bool qc = is_close(r2s, keep, bd);
+          if (qc || in_band(r2s, keep, bd))
+            correct(i, jidx, UNI ? 0 : tag_type(pay_tag(hq)) * 2 + tag_type(jt), qc, bx, by, bz, cx, cy, cz);
         }
       }
-      bx = group_sum(bx, 0);
-      by = group_sum(by, 0);
-      bz = group_sum(bz, 0);
-      if (ln == k << SHIFT) {
-        f[i] += bx * kInvFixF;
-        f[v.N + i] += by * kInvFixF;
-        f[2 * v.N + i] += bz * kInvFixF;
-      }
+      apply(k, bx, by, bz, cx, cy, cz);
     }
   }
   return BandEnergy{e, es, w};
@@ -663,11 +739,11 @@ void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
   using Q = std::conditional_t<FP64, double, int>;     // coordinate type
   constexpr int LV = KMAX == 8 ? 3 : (KMAX == 4 ? 2 : (KMAX == 2 ? 1 : 0));   // log2(KMAX)
   static_assert((1 << LV) == KMAX, "KMAX must be 1, 2, 4 or 8");
-  __shared__ uint32_t list[kTileWaves][kListCap];
-  __shared__ Shift<Q> shifts[kMaxStencil];
+  __shared__ uint32_t list[kTileWaves][kListCap + 65];   // + the padding to a whole step, + 1
+  __shared__ Shift<Q> shifts[kShiftSlots];
   __shared__ dd red[kTileWaves][3];
-  __shared__ int32_t bq[kTileWaves][kBandQueue];   // queued band pairs: j << 4 | type_j << 3 | k
-  __shared__ int bsteps[kTileWaves][kBandSteps];    // flat list position of each band step
+  __shared__ int32_t bq[kTileWaves][kBandQueue];   // queued pairs: j << 6 | type_j << 5 | close << 4 | k
+  __shared__ int bsteps[kTileWaves][kBandSteps];    // flat list position of each recorded step
 
   const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   const int ln = lane();
@@ -684,17 +760,7 @@ void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
   const PayT* __restrict__ pay = static_cast<const PayT*>(v.payload);
 
   // stencil offsets in the payload's units (the same for every wave of the block)
-  {
-    const int R = v.R, W = 2 * R + 1;
-    for (int code = (int)threadIdx.x; code < W * W * W; code += (int)blockDim.x) {
-      const Cell3 o = stencil_offset(code, R);
-      const int ox = o.x, oy = o.y, oz = o.z;
-      if constexpr (FP64)
-        shifts[code] = Shift<Q>{ox * B.edge[0], oy * B.edge[1], oz * B.edge[2]};
-      else
-        shifts[code] = Shift<Q>{ox * B.edge_q[0], oy * B.edge_q[1], oz * B.edge_q[2]};
-    }
-  }
+  load_shifts(v, b, shifts);
   int total = 0, resident = 0;
   if (wact) total = __builtin_amdgcn_readfirstlane(load_list<LIST>(v, B, lc, 0, list[wave]));
   __syncthreads();
@@ -703,7 +769,7 @@ void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
   if (wact) {
     const int hs = __builtin_amdgcn_readfirstlane(cs[B.cell_off + lc]);
     const int hn = __builtin_amdgcn_readfirstlane(cs[B.cell_off + lc + 1]) - hs;
-    const Band bd{cf.band_lo, cf.band_hi};
+    const Band bd = band_of(cf);
     // one type pair (mixed): forces are summed divided by f6 (see pair_fix)
     const float f12_fold = cf.f12_fold;
     const float fscale = UNI ? kInvFixF * cf.f6[0] : kInvFixF;
@@ -767,15 +833,17 @@ void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
           }
         const double rc2_keep = ff.rc2 * (1.0 + 1e-12);
         int m = 0;
-        // kFilter steps per batch with their loads in flight together (lanes past the end
-        // re-read the last entry, a valid payload index and stencil code, and are masked
-        // out); a batch reads all its entries before it writes any
+        // kFilter steps per batch with their loads in flight together; every entry from total
+        // up to and including position tp is the sentinel (load_list pads the list), which
+        // never passes, so positions past the end clamp to tp; a batch reads all its entries
+        // before it writes any
         constexpr int kFilter = FP64 ? 2 : kFilterSteps;
+        const int tp = (total + 63) & ~63;
         for (int t0 = 0; t0 < total; t0 += 64 * kFilter) {
           uint32_t ent[kFilter];
           Q jx[kFilter], jy[kFilter], jz[kFilter];
 #pragma unroll
-          for (int u = 0; u < kFilter; ++u) ent[u] = list[wave][min(t0 + 64 * u + ln, total - 1)];
+          for (int u = 0; u < kFilter; ++u) ent[u] = list[wave][min(t0 + 64 * u + ln, tp)];
 #pragma unroll
           for (int u = 0; u < kFilter; ++u) {
             const PayT q = pay[ent[u] >> 7];
@@ -793,16 +861,16 @@ void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
               pass = dx * dx + dy * dy + dz * dz < rc2_keep;
             else
               pass = r2_fix((float)dx, (float)dy, (float)dz) < bd.hi;
-            pass = pass && t0 + 64 * u + ln < total;
             const uint64_t bm = __builtin_amdgcn_ballot_w64(pass);
             if (pass) list[wave][m + lanes_below(bm)] = ent[u];
             m += __popcll(bm);
           }
         }
+        if (ln < ((m + 63) & ~63) - m) list[wave][m + ln] = kSentinelEntry;   // pad to whole steps
         ncand = m;
         resident = kCompacted;
       }
-      int nsteps = 0;       // candidate steps with a band pair (wave-uniform)
+      int nsteps = 0;       // candidate steps with a band pair or a close contact (wave-uniform)
       int32_t bmax = 0;     // bits of the largest r2s counted since the last band check
       for (int c0 = 0; c0 < ncand; c0 += kListCap) {
         if (resident != kCompacted && c0 != resident) {
@@ -811,19 +879,19 @@ void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
         }
         const int cn = min(kListCap, ncand - c0);
         for (int t0 = 0; t0 < cn; t0 += 64) {
-          const bool act = t0 + ln < cn;
-          // lanes past the end re-read entry t0, a valid candidate that keep then masks out
-          const uint32_t ent = list[wave][t0 + (act ? ln : 0)];
+          // the list is padded to whole steps with the sentinel, which lies beyond the cutoff
+          const uint32_t ent = list[wave][t0 + ln];
           const PayT q = pay[ent >> 7];
           const Shift<Q> sh = shifts[ent & 127];
           const int32_t jt = pay_tag(q);
           const Q jx = q.x + sh.x, jy = q.y + sh.y, jz = q.z + sh.z;
           const int32_t jidx = tag_index(jt);
           const int jtype = tag_type(jt);
+          bool near = false;    // a close contact on this lane in this step (mixed)
 #pragma unroll
           for (int k = 0; k < KMAX; ++k) {
             if (k < kc) {
-              const bool keep = act && (uint32_t)(jidx - lo[k]) > span[k];
+              const bool keep = (uint32_t)(jidx - lo[k]) > span[k];
               const int tt = UNI ? 0 : hti[k] * 2 + jtype;
               if constexpr (FP64)
                 pair_f64<ENERGY>(hx[k] - jx, hy[k] - jy, hz[k] - jz, keep, ff.rc2, pick(cd.f12, tt),
@@ -833,12 +901,12 @@ void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
                 pair_fix<ENERGY, BRANCHLESS, UNI>(hx[k] - jx, hy[k] - jy, hz[k] - jz, keep, bd,
                                                   UNI ? f12_fold : pick(cf.f12, tt), pick(cf.f6, tt),
                                                   pick(cf.e12, tt), pick(cf.e6, tt), pick(cf.ecut, tt), ax[k],
-                                                  ay[k], az[k], e, es, w, bmax);
+                                                  ay[k], az[k], e, es, w, bmax, near);
             }
           }
           if constexpr (!FP64) {
-            // rare: a lane counted a pair in the cutoff band; note the step
-            if (__builtin_amdgcn_ballot_w64(bmax >= __float_as_int(bd.lo)) != 0) {
+            // rare: a lane counted a pair in the cutoff band or met a close contact; note the step
+            if (__builtin_amdgcn_ballot_w64(bmax >= __float_as_int(bd.lo) || near) != 0) {
               bmax = 0;
               if (nsteps < kBandSteps && ln == 0) bsteps[wave][nsteps] = c0 + t0;
               ++nsteps;
@@ -896,9 +964,9 @@ void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
       }
       if constexpr (!FP64) {
         if (nsteps > 0) {
-          const BandEnergy be = settle_band_group<ENERGY, UNI, LIST, 6 - LV>(v, ff.chain_len, ff.excl, ff.rc2, cf, B, bd, lc,
-                                                               total, ncand, list[wave], resident, shifts, bsteps[wave],
-                                                               bq[wave], pay, hs, g0, kc, nsteps);
+          const BandEnergy be = settle_group<ENERGY, UNI, LIST, 6 - LV>(v, ff.chain_len, ff.excl, ff.rc2, cf, cd, B, bd,
+                                                                       lc, total, ncand, list[wave], resident, shifts,
+                                                                       bsteps[wave], bq[wave], pay, hs, g0, kc, nsteps);
           if (ENERGY) {
             e += be.e;
             es += be.es;
@@ -1005,7 +1073,7 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_lj_half(Views v, FFDev ff, 
   constexpr int KMAX = FP64 ? 4 : 8;
   constexpr int LV = FP64 ? 2 : 3;
   __shared__ uint32_t list[kTileWaves][kListCap];
-  __shared__ Shift<Q> shifts[kMaxStencil];
+  __shared__ Shift<Q> shifts[kShiftSlots];
   __shared__ dd red[kTileWaves][3];
 
   const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
@@ -1018,15 +1086,7 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_lj_half(Views v, FFDev ff, 
   const bool wact = lc < B.n_cells;
   const PayT* __restrict__ pay = static_cast<const PayT*>(v.payload);
   const int R = v.R, W = 2 * R + 1, ctr = (W * W * W - 1) / 2;
-  {
-    for (int code = (int)threadIdx.x; code < W * W * W; code += (int)blockDim.x) {
-      const Cell3 o = stencil_offset(code, R);
-      if constexpr (FP64)
-        shifts[code] = Shift<Q>{o.x * B.edge[0], o.y * B.edge[1], o.z * B.edge[2]};
-      else
-        shifts[code] = Shift<Q>{o.x * B.edge_q[0], o.y * B.edge_q[1], o.z * B.edge_q[2]};
-    }
-  }
+  load_shifts(v, v.lj_blk_box[blk], shifts);
   int total = 0, resident = 0;
   if (wact) total = __builtin_amdgcn_readfirstlane(fill_list_half(v, B, lc, 0, list[wave]));
   __syncthreads();
@@ -1035,7 +1095,7 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_lj_half(Views v, FFDev ff, 
   if (wact) {
     const int hs = __builtin_amdgcn_readfirstlane(v.cell_start[B.cell_off + lc]);
     const int hn = __builtin_amdgcn_readfirstlane(v.cell_start[B.cell_off + lc + 1]) - hs;
-    const Band bd = make_band(ff.rc2);
+    const Band bd = band_of(cf);
     // accumulator units per unit of the lane sums: mixed sums are in 2^25 (fixed-point) units
     const double scale = FP64 ? kHalfFix : kHalfFix * (double)kInvFixF;
     unsigned long long* __restrict__ acc = v.f_acc;
@@ -1128,6 +1188,20 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_lj_half(Views v, FFDev ff, 
                   double d[3], r2;
                   hit = inside_cutoff_f64(v.pos, N, B, hidx[k], jidx, ff.rc2, d, r2);
                 }
+                if (is_close(r2s, keep, bd)) {
+                  // rare: a close contact, evaluated in FP64 and deposited on both atoms at once
+                  double d[3], r2, fx = 0.0, fy = 0.0, fz = 0.0;
+                  inside_cutoff_f64(v.pos, N, B, hidx[k], jidx, ff.rc2, d, r2);
+                  add_close_pair<ENERGY>(d, r2, pick(cd.f12, tt), pick(cd.f6, tt), pick(cd.e12, tt),
+                                         pick(cd.e6, tt), pick(cd.ecut, tt), fx, fy, fz, e, es, w);
+                  deposit(acc + hidx[k], fx * kHalfFix);
+                  deposit(acc + N + hidx[k], fy * kHalfFix);
+                  deposit(acc + 2 * N + hidx[k], fz * kHalfFix);
+                  deposit(acc + jidx, -fx * kHalfFix);
+                  deposit(acc + N + jidx, -fy * kHalfFix);
+                  deposit(acc + 2 * N + jidx, -fz * kHalfFix);
+                  hit = false;
+                }
                 if (hit) {
                   const float r2 = r2s * kInvFix2F;
                   const float r2i = rcp_f(r2);
@@ -1193,11 +1267,12 @@ __global__ __launch_bounds__(256) void k_half_finish(Views v) {
 // sorted order, entry-major ([nl_cap][64]), so that the force kernel's 64 lanes read 64
 // consecutive words per step.
 template <bool FP64, int KMAX>
-__global__ __launch_bounds__(64 * kTileWaves) void k_nl_build(Views v, FFDev ff) {
+__global__ __launch_bounds__(64 * kTileWaves) void k_nl_build(Views v, FFDev ff, const int32_t* __restrict__ gate) {
+  if (gate && *gate == 0) return;   // no rebuild this step
   using PayT = std::conditional_t<FP64, Pay64, int4>;
   using Q = std::conditional_t<FP64, double, int>;
   __shared__ uint32_t list[kTileWaves][kListCap];
-  __shared__ Shift<Q> shifts[kMaxStencil];
+  __shared__ Shift<Q> shifts[kShiftSlots];
 
   const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   const int ln = lane();
@@ -1208,17 +1283,7 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_nl_build(Views v, FFDev ff)
   const int lc = (blk - B.cell_blk_off) * kTileWaves + wave;
   const bool wact = lc < B.n_cells;
   const PayT* __restrict__ pay = static_cast<const PayT*>(v.payload);
-  {
-    const int R = v.R, W = 2 * R + 1;
-    for (int code = (int)threadIdx.x; code < W * W * W; code += (int)blockDim.x) {
-      const Cell3 o = stencil_offset(code, R);
-      const int ox = o.x, oy = o.y, oz = o.z;
-      if constexpr (FP64)
-        shifts[code] = Shift<Q>{ox * B.edge[0], oy * B.edge[1], oz * B.edge[2]};
-      else
-        shifts[code] = Shift<Q>{ox * B.edge_q[0], oy * B.edge_q[1], oz * B.edge_q[2]};
-    }
-  }
+  load_shifts(v, v.cell_blk_box[blk], shifts);
   int total = 0, resident = 0;
   if (wact) total = __builtin_amdgcn_readfirstlane(fill_list(v, B, lc, 0, list[wave]));
   __syncthreads();
@@ -1297,12 +1362,10 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_nl_build(Views v, FFDev ff)
         }
       }
     }
+    // the full count: above cap the force kernel walks this atom's stencil instead
 #pragma unroll
     for (int k = 0; k < KMAX; ++k)
-      if (k < kc && ln == 0) {
-        v.nl_count[hs + g0 + k] = min(cnt[k], cap);
-        if (cnt[k] > cap) atomicOr(v.err, (int)kErrNlFull);
-      }
+      if (k < kc && ln == 0) v.nl_count[hs + g0 + k] = cnt[k];
   }
 }
 
@@ -1312,11 +1375,12 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_nl_build(Views v, FFDev ff)
 // the stencil (k_lj_tile<LIST>): fewer candidates, the same coalesced loads.  Home atoms
 // and excluded partners stay in the list (the force kernel tests exclusions per pair).
 template <bool FP64>
-__global__ __launch_bounds__(64 * kTileWaves) void k_nl_build_tile(Views v, FFDev ff) {
+__global__ __launch_bounds__(64 * kTileWaves) void k_nl_build_tile(Views v, FFDev ff, const int32_t* __restrict__ gate) {
+  if (gate && *gate == 0) return;   // no rebuild this step
   using PayT = std::conditional_t<FP64, Pay64, int4>;
   using Q = std::conditional_t<FP64, double, int>;
   __shared__ uint32_t list[kTileWaves][kListCap];
-  __shared__ Shift<Q> shifts[kMaxStencil];
+  __shared__ Shift<Q> shifts[kShiftSlots];
 
   const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   const int ln = lane();
@@ -1327,17 +1391,7 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_nl_build_tile(Views v, FFDe
   const int lc = (blk - B.cell_blk_off) * kTileWaves + wave;
   const bool wact = lc < B.n_cells;
   const PayT* __restrict__ pay = static_cast<const PayT*>(v.payload);
-  {
-    const int R = v.R, W = 2 * R + 1;
-    for (int code = (int)threadIdx.x; code < W * W * W; code += (int)blockDim.x) {
-      const Cell3 o = stencil_offset(code, R);
-      const int ox = o.x, oy = o.y, oz = o.z;
-      if constexpr (FP64)
-        shifts[code] = Shift<Q>{ox * B.edge[0], oy * B.edge[1], oz * B.edge[2]};
-      else
-        shifts[code] = Shift<Q>{ox * B.edge_q[0], oy * B.edge_q[1], oz * B.edge_q[2]};
-    }
-  }
+  load_shifts(v, v.cell_blk_box[blk], shifts);
   int total = 0, resident = 0;
   if (wact) total = __builtin_amdgcn_readfirstlane(fill_list(v, B, lc, 0, list[wave]));
   __syncthreads();
@@ -1402,10 +1456,8 @@ __global__ __launch_bounds__(64 * kTileWaves) void k_nl_build_tile(Views v, FFDe
       cnt += __popcll(m);
     }
   }
-  if (ln == 0) {
-    v.nl_count[B.cell_off + lc] = min(cnt, cap);
-    if (cnt > cap) atomicOr(v.err, (int)kErrNlFull);
-  }
+  // the full count: above cap the force kernel streams this cell's stencil instead
+  if (ln == 0) v.nl_count[B.cell_off + lc] = cnt;
 }
 
 // LJ force from the lists: one lane per atom of sorted order, walking its list; the
@@ -1418,21 +1470,11 @@ __global__ __launch_bounds__(kLjNlBlock) void k_lj_nl(Views v, FFDev ff, LjPair<
   using PayT = std::conditional_t<FP64, Pay64, int4>;
   using P = std::conditional_t<FP64, double, float>;
   using Q = std::conditional_t<FP64, double, int>;
-  __shared__ Shift<Q> shifts[kMaxStencil];
+  __shared__ Shift<Q> shifts[kShiftSlots];
   __shared__ dd red[kLjNlBlock / 64][3];
   const BoxDev& B = v.boxes[v.lj_blk_box[blockIdx.x]];
   const int local = ((int)blockIdx.x - B.lj_blk_off) * kLjNlBlock + (int)threadIdx.x;
-  {
-    const int R = v.R, W = 2 * R + 1;
-    for (int code = (int)threadIdx.x; code < W * W * W; code += (int)blockDim.x) {
-      const Cell3 o = stencil_offset(code, R);
-      const int ox = o.x, oy = o.y, oz = o.z;
-      if constexpr (FP64)
-        shifts[code] = Shift<Q>{ox * B.edge[0], oy * B.edge[1], oz * B.edge[2]};
-      else
-        shifts[code] = Shift<Q>{ox * B.edge_q[0], oy * B.edge_q[1], oz * B.edge_q[2]};
-    }
-  }
+  load_shifts(v, v.lj_blk_box[blockIdx.x], shifts);
   __syncthreads();
   double e = 0.0, es = 0.0, w = 0.0;
   if (local < B.n_atoms) {
@@ -1444,7 +1486,7 @@ __global__ __launch_bounds__(kLjNlBlock) void k_lj_nl(Views v, FFDev ff, LjPair<
     const int n = v.nl_count[s];
     const uint32_t* __restrict__ row =
         v.nl_list + B.nl_off + (int64_t)(local >> 6) * 64 * v.nl_cap + (local & 63);
-    const Band bd = make_band(ff.rc2);
+    const Band bd = band_of(cf);
     const float f12_fold = cf.f12[0] / cf.f6[0];
     // kNlSums interleaved partial sums: shorter FP32 summation chains, and that many list
     // entries in flight per lane
@@ -1452,39 +1494,72 @@ __global__ __launch_bounds__(kLjNlBlock) void k_lj_nl(Views v, FFDev ff, LjPair<
     P ax[kNlSums], ay[kNlSums], az[kNlSums];
 #pragma unroll
     for (int u = 0; u < kNlSums; ++u) ax[u] = ay[u] = az[u] = (P)0;
+    double cx = 0.0, cy = 0.0, cz = 0.0;   // close contacts (mixed), FP64
     int32_t bmax = 0;
-    for (int t0 = 0; t0 < n; t0 += kNlSums) {
+    // one candidate (payload q at stencil shift sh) into partial sum u
+    auto one = [&](const PayT& q, const Shift<Q>& sh, bool keep, int u) {
+      const int32_t tj = pay_tag(q);
+      const int tt = UNI ? 0 : ti * 2 + tag_type(tj);
+      if constexpr (FP64) {
+        pair_f64<ENERGY>(hq.x - (q.x + sh.x), hq.y - (q.y + sh.y), hq.z - (q.z + sh.z), keep, ff.rc2,
+                         pick(cd.f12, tt), pick(cd.f6, tt), pick(cd.e12, tt), pick(cd.e6, tt), pick(cd.ecut, tt),
+                         ax[u], ay[u], az[u], e, es, w);
+      } else {
+        const int dqx = hq.x - (q.x + sh.x), dqy = hq.y - (q.y + sh.y), dqz = hq.z - (q.z + sh.z);
+        bool near = false;
+        const float r2s = pair_fix<ENERGY, false, UNI>(dqx, dqy, dqz, keep, bd, UNI ? f12_fold : pick(cf.f12, tt),
+                                                       pick(cf.f6, tt), pick(cf.e12, tt), pick(cf.e6, tt),
+                                                       pick(cf.ecut, tt), ax[u], ay[u], az[u], e, es, w, bmax, near);
+        double d[3], r2;
+        if (near) {   // rare: a close contact, in FP64
+          inside_cutoff_f64(v.pos, v.N, B, i, tag_index(tj), ff.rc2, d, r2);
+          add_close_pair<ENERGY>(d, r2, pick(cd.f12, tt), pick(cd.f6, tt), pick(cd.e12, tt), pick(cd.e6, tt),
+                                 pick(cd.ecut, tt), cx, cy, cz, e, es, w);
+        }
+        if (in_band(r2s, keep, bd) && !inside_cutoff_f64(v.pos, v.N, B, i, tag_index(tj), ff.rc2, d, r2)) {
+          // counted above as inside; in the folded form the sums are divided by f6
+          float bx = 0.0f, by = 0.0f, bz = 0.0f;
+          remove_band_pair<ENERGY>(d, r2, pick(cf.f12, tt), pick(cf.f6, tt), pick(cf.e12, tt), pick(cf.e6, tt),
+                                   pick(cf.ecut, tt), bx, by, bz, e, es, w);
+          const float sc = UNI ? 1.0f / cf.f6[0] : 1.0f;
+          ax[u] += bx * sc;
+          ay[u] += by * sc;
+          az[u] += bz * sc;
+        }
+      }
+    };
+    if (n <= v.nl_cap) {
+      for (int t0 = 0; t0 < n; t0 += kNlSums) {
 #pragma unroll
-      for (int u = 0; u < kNlSums; ++u) {
-        const int t = t0 + u;
-        if (t < n) {
-          const uint32_t ent = row[(int64_t)t * 64];
-          const PayT q = pay[ent >> 7];
-          const Shift<Q> sh = shifts[ent & 127];
-          const int32_t tj = pay_tag(q);
-          const int tt = UNI ? 0 : ti * 2 + tag_type(tj);
-          if constexpr (FP64) {
-            pair_f64<ENERGY>(hq.x - (q.x + sh.x), hq.y - (q.y + sh.y), hq.z - (q.z + sh.z), true, ff.rc2,
-                             pick(cd.f12, tt), pick(cd.f6, tt), pick(cd.e12, tt), pick(cd.e6, tt),
-                             pick(cd.ecut, tt), ax[u], ay[u], az[u], e, es, w);
-          } else {
-            const int dqx = hq.x - (q.x + sh.x), dqy = hq.y - (q.y + sh.y), dqz = hq.z - (q.z + sh.z);
-            const float r2s = pair_fix<ENERGY, false, UNI>(dqx, dqy, dqz, true, bd,
-                                                           UNI ? f12_fold : pick(cf.f12, tt), pick(cf.f6, tt),
-                                                           pick(cf.e12, tt), pick(cf.e6, tt), pick(cf.ecut, tt),
-                                                           ax[u], ay[u], az[u], e, es, w, bmax);
-            double d[3], r2;
-            if (in_band(r2s, true, bd) && !inside_cutoff_f64(v.pos, v.N, B, i, tag_index(tj), ff.rc2, d, r2)) {
-              // counted above as inside; in the folded form the sums are divided by f6
-              float bx = 0.0f, by = 0.0f, bz = 0.0f;
-              remove_band_pair<ENERGY>(d, r2, pick(cf.f12, tt), pick(cf.f6, tt), pick(cf.e12, tt),
-                                       pick(cf.e6, tt), pick(cf.ecut, tt), bx, by, bz, e, es, w);
-              const float sc = UNI ? 1.0f / cf.f6[0] : 1.0f;
-              ax[u] += bx * sc;
-              ay[u] += by * sc;
-              az[u] += bz * sc;
-            }
+        for (int u = 0; u < kNlSums; ++u) {
+          const int t = t0 + u;
+          if (t < n) {
+            const uint32_t ent = row[(int64_t)t * 64];
+            one(pay[ent >> 7], shifts[ent & 127], true, u);
           }
+        }
+      }
+    } else {
+      // the list outgrew its capacity: walk the stencil of the build's bins (every atom has moved
+      // less than half the skin since, and the stencil covers rc + skin), excluding 1-2/1-3 here
+      const int32_t c0 = chain_first(i, ff);
+      const int32_t lo = max(i - ff.excl, c0);
+      const uint32_t span = (uint32_t)(min(i + ff.excl, c0 + ff.chain_len - 1) - lo);
+      const int R = v.R, W = 2 * R + 1;
+      const Cell3 k3 = cell_coords(v.scell[s] - B.cell_off, B);
+      for (int code = 0; code < W * W * W; ++code) {
+        const Cell3 o = stencil_offset(code, R);
+        int nx = k3.x + o.x, ny = k3.y + o.y, nz = k3.z + o.z;
+        nx += nx < 0 ? B.M[0] : 0;
+        nx -= nx >= B.M[0] ? B.M[0] : 0;
+        ny += ny < 0 ? B.M[1] : 0;
+        ny -= ny >= B.M[1] ? B.M[1] : 0;
+        nz += nz < 0 ? B.M[2] : 0;
+        nz -= nz >= B.M[2] ? B.M[2] : 0;
+        const int c = B.cell_off + nx + B.M[0] * (ny + B.M[1] * nz);
+        for (int t = v.cell_start[c]; t < v.cell_start[c + 1]; ++t) {
+          const PayT q = pay[t];
+          one(q, shifts[code], (uint32_t)(tag_index(pay_tag(q)) - lo) > span, 0);
         }
       }
     }
@@ -1498,9 +1573,9 @@ __global__ __launch_bounds__(kLjNlBlock) void k_lj_nl(Views v, FFDev ff, LjPair<
     P fx = ax[0], fy = ay[0], fz = az[0];
     if constexpr (!FP64) {
       const float sc = UNI ? kInvFixF * cf.f6[0] : kInvFixF;
-      fx *= sc;
-      fy *= sc;
-      fz *= sc;
+      fx = (float)((double)(fx * sc) + cx);
+      fy = (float)((double)(fy * sc) + cy);
+      fz = (float)((double)(fz * sc) + cz);
     }
     P* f = static_cast<P*>(v.f_lj);
     f[i] = fx;
@@ -1521,9 +1596,14 @@ LjPair<P> make_pair(const FFDev& ff) {
     c.ecut[t] = (P)ff.ecut[t];
   }
   c.f12_fold = c.f12[0] / c.f6[0];
-  // the same expressions as make_band (products only, so no contraction can differ)
   c.band_lo = (float)(ff.rc2 * kFix * kFix * (1.0 - kBand));
   c.band_hi = (float)(ff.rc2 * kFix * kFix * (1.0 + kBand));
+  // close contacts: r below kCloseSigma times the smallest sigma of a type pair that interacts
+  // (sigma^6 = e12 / e6)
+  double s6 = 0.0;
+  for (int t = 0; t < 4; ++t)
+    if (ff.e6[t] > 0.0) s6 = s6 > 0.0 ? std::min(s6, ff.e12[t] / ff.e6[t]) : ff.e12[t] / ff.e6[t];
+  c.close = (float)(kCloseSigma * kCloseSigma * std::cbrt(s6) * kFix * kFix);
   return c;
 }
 
@@ -1550,26 +1630,26 @@ int64_t lj_blocks_for_box(int kernel, int64_t n_atoms, int64_t n_cells) {
   return (n_atoms + kLjAtomBlock - 1) / kLjAtomBlock;
 }
 
-void launch_nl_build(const Views& v, const FFDev& ff, bool fp32, int kernel, hipStream_t s) {
+void launch_nl_build(const Views& v, const FFDev& ff, bool fp32, int kernel, hipStream_t s, const int32_t* gate) {
   dim3 g((v.n_cell_blocks + kXcds - 1) / kXcds * kXcds), b(64 * kTileWaves);
   if (kernel == 5) {
     if (fp32)
-      hipLaunchKernelGGL((k_nl_build_tile<false>), g, b, 0, s, v, ff);
+      hipLaunchKernelGGL((k_nl_build_tile<false>), g, b, 0, s, v, ff, gate);
     else
-      hipLaunchKernelGGL((k_nl_build_tile<true>), g, b, 0, s, v, ff);
+      hipLaunchKernelGGL((k_nl_build_tile<true>), g, b, 0, s, v, ff, gate);
     return;
   }
   if (fp32)
-    hipLaunchKernelGGL((k_nl_build<false, kTileHomesMixed>), g, b, 0, s, v, ff);
+    hipLaunchKernelGGL((k_nl_build<false, kTileHomesMixed>), g, b, 0, s, v, ff, gate);
   else
-    hipLaunchKernelGGL((k_nl_build<true, 4>), g, b, 0, s, v, ff);
+    hipLaunchKernelGGL((k_nl_build<true, 4>), g, b, 0, s, v, ff, gate);
 }
 
-void launch_lj_nl(const Views& v, const FFDev& ff, bool fp32, int kernel, bool energy, bool build_step,
-                  hipStream_t s) {
+// Neighbour-list forces always read the current payload (the build's right after a rebuild).
+void launch_lj_nl(const Views& v, const FFDev& ff, bool fp32, int kernel, bool energy, hipStream_t s) {
   const LjPair<float> cf = make_pair<float>(ff);
   const LjPair<double> cd = make_pair<double>(ff);
-  const void* pay = build_step ? v.payload : v.pay_cur;
+  const void* pay = v.pay_cur;
   if (kernel == 5) {   // per-cell lists through the cell tile, reading the current payload
     Views w = v;
     w.payload = const_cast<void*>(pay);

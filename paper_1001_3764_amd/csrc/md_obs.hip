@@ -14,6 +14,8 @@
 //   k_obs_reduce     per bin, the block partials in block order (64-bit)
 //   k_obs_chains     one wavefront per chain: the chain unwrapped bond by bond (a wave
 //                    prefix sum per 64 atoms), centre of mass, then R_g^2 and R_ee
+//   k_ree,           the end-to-end vector autocorrelation (Fig. 8): each chain's R_ee
+//   k_ree_reduce     against the one stored at the reference time, summed per box
 #include "md_internal.h"
 
 namespace mdk {
@@ -206,6 +208,61 @@ __global__ __launch_bounds__(256) void k_obs_chains(Views v, FFDev ff, int b, in
   }
 }
 
+// End-to-end vector autocorrelation (Fig. 8).  One wavefront per chain of box b: R, the sum
+// of the chain's minimum-imaged bonds (each lane sums every 64th bond, then a fixed-order wave
+// sum).  REF: store R as the reference ree0[c]; otherwise write the chain's terms
+// part[2 c] = R . ree0[c] and part[2 c + 1] = |ree0[c]|^2.
+template <bool REF>
+__global__ __launch_bounds__(256) void k_ree(Views v, int b, int chain_len, double* ree0, double* part) {
+  const BoxDev& B = v.boxes[b];
+  const int n_chains = B.n_atoms / chain_len;
+  const int ch = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  if (ch >= n_chains) return;
+  const int ln = lane();
+  const int64_t N = v.N;
+  const int64_t a0 = (int64_t)B.atom_off + (int64_t)ch * chain_len;
+  double r[3] = {0.0, 0.0, 0.0};
+  for (int p = 1 + ln; p < chain_len; p += 64)
+    for (int q = 0; q < 3; ++q)
+      r[q] += mi_rn(__dadd_rn(v.pos[q * N + a0 + p], -v.pos[q * N + a0 + p - 1]), B.L[q], B.invL[q]);
+  for (int q = 0; q < 3; ++q) r[q] = wave_sum(r[q]);
+  if (ln != 0) return;
+  const int64_t c = (int64_t)B.atom_off / chain_len + ch;
+  if (REF) {
+    for (int q = 0; q < 3; ++q) ree0[3 * c + q] = r[q];
+  } else {
+    const double* r0 = ree0 + 3 * c;
+    part[2 * c] = r[0] * r0[0] + r[1] * r0[1] + r[2] * r0[2];
+    part[2 * c + 1] = r0[0] * r0[0] + r0[1] * r0[1] + r0[2] * r0[2];
+  }
+}
+
+// Box b's autocorrelation: the chain terms of k_ree summed in chain order as double-double
+// (each thread a contiguous run of chains, then the runs in thread order), out[b] = num / den.
+__global__ __launch_bounds__(256) void k_ree_reduce(Views v, int b, int chain_len, const double* part,
+                                                    double* out) {
+  __shared__ dd sh[256][2];
+  const BoxDev& B = v.boxes[b];
+  const int64_t c0 = (int64_t)B.atom_off / chain_len;
+  const int64_t n = B.n_atoms / chain_len;
+  const int64_t per = (n + 255) / 256;
+  dd num = dd_from(0.0), den = dd_from(0.0);
+  for (int64_t c = (int64_t)threadIdx.x * per; c < min(n, ((int64_t)threadIdx.x + 1) * per); ++c) {
+    num = dd_add(num, dd_from(part[2 * (c0 + c)]));
+    den = dd_add(den, dd_from(part[2 * (c0 + c) + 1]));
+  }
+  sh[threadIdx.x][0] = num;
+  sh[threadIdx.x][1] = den;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int t = 1; t < 256; ++t) {
+      num = dd_add(num, sh[t][0]);
+      den = dd_add(den, sh[t][1]);
+    }
+    out[b] = (num.hi + num.lo) / (den.hi + den.lo);
+  }
+}
+
 int obs_blocks(int64_t n) {
   const int64_t g = (n + kAtomBlock - 1) / kAtomBlock;
   return (int)(g < 1 ? 1 : (g > kObsBlocks ? kObsBlocks : g));
@@ -233,6 +290,16 @@ void launch_obs_chains(const Views& v, const FFDev& ff, int b, int64_t n_chains,
                        hipStream_t s) {
   const int64_t threads = n_chains * 64;
   hipLaunchKernelGGL(k_obs_chains, dim3((int)((threads + 255) / 256)), dim3(256), 0, s, v, ff, b, chain_len, out);
+}
+
+void launch_ree(const Views& v, int b, int64_t n_chains, int chain_len, bool reference, double* out, hipStream_t s) {
+  const dim3 g((unsigned)((n_chains * 64 + 255) / 256)), blk(256);
+  if (reference) {
+    hipLaunchKernelGGL(k_ree<true>, g, blk, 0, s, v, b, chain_len, v.ree0, v.ree_part);
+  } else {
+    hipLaunchKernelGGL(k_ree<false>, g, blk, 0, s, v, b, chain_len, v.ree0, v.ree_part);
+    hipLaunchKernelGGL(k_ree_reduce, dim3(1), dim3(256), 0, s, v, b, chain_len, (const double*)v.ree_part, out);
+  }
 }
 
 }  // namespace mdk

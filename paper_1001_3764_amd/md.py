@@ -90,6 +90,9 @@ def load():
         "md_tuning": (S, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
         "md_destroy": (S, [_P]),
         "md_observables": (S, [_P, _P, _P, _P, _P]),
+        "md_ree_reference": (S, [_P]),
+        "md_ree_acf": (S, [_P, _P]),
+        "md_list_builds": (S, [_P, ctypes.POINTER(_I64)]),
         "md_status_string": (ctypes.c_char_p, [S]),
         "md_last_error": (ctypes.c_char_p, [_P]),
     }
@@ -238,14 +241,18 @@ def md_tuning(ctx):
     return r.value, k.value
 
 
-def rdf_from_counts(counts, n_atoms, box, rmax):
-    """g(r) at the bin centres from md_observables' pair counts of one box: counts over the
-    ideal-gas expectation N (N - 1) / 2 * shell volume / V."""
-    counts = np.asarray(counts, dtype=np.float64)
-    edges = np.arange(counts.size + 1) * (rmax / counts.size)
-    shell = 4.0 / 3.0 * np.pi * (edges[1:] ** 3 - edges[:-1] ** 3)
-    ideal = n_atoms * (n_atoms - 1) / 2.0 * shell / float(np.prod(box))
-    return 0.5 * (edges[1:] + edges[:-1]), counts / ideal
+def md_ree_reference(ctx):
+    _check(load().md_ree_reference(ctx), "md_ree_reference", ctx)
+
+
+def md_ree_acf(ctx, out):
+    _check(load().md_ree_acf(ctx, out.data_ptr()), "md_ree_acf", ctx)
+
+
+def md_list_builds(ctx):
+    n = _I64()
+    _check(load().md_list_builds(ctx, ctypes.byref(n)), "md_list_builds", ctx)
+    return n.value
 
 
 def md_destroy(ctx):
@@ -329,6 +336,19 @@ class MDSystem:
 
     def tuning(self):
         return md_tuning(self.ctx)
+
+    def list_builds(self):
+        return md_list_builds(self.ctx)
+
+    def ree_reference(self):
+        md_ree_reference(self.ctx)
+
+    def ree_acf(self):
+        """End-to-end vector autocorrelation of each box against the reference (md_ree_acf)."""
+        out = torch.zeros(self.n_boxes, dtype=torch.float64, device=self.device)
+        md_ree_acf(self.ctx, out)
+        torch.cuda.synchronize(self.device)
+        return out.cpu().numpy()
 
     def grid(self, box=0):
         return md_grid(self.ctx, box)

@@ -105,7 +105,7 @@ def test_workspace_bytes_and_validation(md, ff):
         dict(lj_kernel=4),
         dict(lj_kernel=7),
         dict(nl_skin=-0.5),
-        dict(nl_skin=1.0, nl_every=0),
+        dict(nl_skin=1.0, nl_every=-1),
         dict(T0=(float("nan"),)),
         dict(box=((44.376, 0.0, 44.376),)),
     ]
@@ -120,6 +120,29 @@ def test_workspace_bytes_and_validation(md, ff):
     assert workspace(md, ff, cfg)[0] == md.MD_ERR_ARG
     # 25 A box: fewer than three cells of edge >= rc per dimension
     assert workspace(md, ff, config(md, n_chains=(1,), box=((25.0, 25.0, 25.0),)))[0] == md.MD_ERR_BOX_TOO_SMALL
+
+
+def test_fixed_point_range_is_enforced(md, ff):
+    """The mixed payload holds coordinates as int32 in 2^-25 A: (R + 2) * edge + skin must stay
+    below 63 A (R stencil cells and the list's padding sentinel one edge further).  A 30 A
+    cutoff fits at R = 3 (edges of 11.1 A) but not at R = 1 or 2 (33.3 and 16.7 A); a 45 A
+    cutoff fits no tile stencil; FP64 has no such limit; the skin counts against it."""
+    big = dict(n_chains=(10,), box=((100.0, 100.0, 100.0),))
+    ff30 = dict(ff, rc=30.0)
+    ff45 = dict(ff, rc=45.0)
+    box150 = dict(n_chains=(10,), box=((150.0, 150.0, 150.0),))
+    assert workspace(md, ff30, config(md, cell_div=1, **big))[0] == md.MD_ERR_ARG
+    assert workspace(md, ff30, config(md, cell_div=2, lj_kernel=2, **big))[0] == md.MD_ERR_ARG
+    assert workspace(md, ff30, config(md, cell_div=0, lj_kernel=0, **big))[0] == md.MD_ERR_ARG
+    assert workspace(md, ff30, config(md, cell_div=3, lj_kernel=1, **big))[0] == md.MD_OK
+    assert workspace(md, ff30, config(md, cell_div=1, precision="fp64", **big))[0] == md.MD_OK
+    assert workspace(md, ff45, config(md, cell_div=0, lj_kernel=0, **box150))[0] == md.MD_ERR_ARG
+    assert workspace(md, ff45, config(md, cell_div=0, lj_kernel=0, precision="fp64", **box150))[0] == md.MD_OK
+    # neighbour lists, R = 1: a 2 A skin gives 14.8 A cells (3 * 14.8 + 2 < 63); a 25 A skin in a
+    # 200 A box gives 40 A cells (3 * 40 + 25 >= 63)
+    assert workspace(md, ff, config(md, cell_div=1, lj_kernel=0, nl_skin=2.0, nl_every=0))[0] == md.MD_OK
+    assert workspace(md, ff, config(md, n_chains=(200,), box=((200.0, 200.0, 200.0),), cell_div=1, lj_kernel=0,
+                                    nl_skin=25.0, nl_every=0))[0] == md.MD_ERR_ARG
 
 
 def test_static_setup_refusals(md, ff):

@@ -13,14 +13,16 @@ from pe_melt import WORKLOADS, build_melts
 
 pytestmark = pytest.mark.gpu
 
-TOL = 1e-5   # FP32 force error, per atom against max(|F_i|, F_rms)
+TOL = 1e-5   # FP32 forces, norm-wise: max_i |F_gpu,i - F_ora,i| / F_rms(oracle)
 
 
-def rel_err(d, scale):
-    """max_i |d_i| / max(|scale_i|, rms_i |scale_i|) over atoms (columns)."""
-    fn = np.sqrt(np.sum(scale ** 2, axis=0))
-    frms = np.sqrt(np.mean(fn ** 2))
-    return float(np.max(np.sqrt(np.sum(d ** 2, axis=0)) / np.maximum(fn, frms)))
+def norm_err(d, frms):
+    """max_i |d_i| / frms over atoms (columns)."""
+    return float(np.max(np.sqrt(np.sum(d ** 2, axis=0))) / frms)
+
+
+def rms(f):
+    return float(np.sqrt(np.mean(np.sum(f ** 2, axis=0))))
 
 
 def energy_close(e, ref, keys=("e_lj", "e_bond", "e_angle", "e_dih")):
@@ -57,21 +59,32 @@ def check_bins(s, melt, b=0):
     np.testing.assert_array_equal(atoms[lo:hi] - atom_off, oatoms)
 
 
-def check_sampled_forces(ff, s, melt, n_sample, seed, atom_off=0, include_max=True):
+def check_sampled_forces(ff, s, melt, n_sample, seed, atom_off=0, full=True):
+    """Forces against the oracle at the same positions, norm-wise over the oracle's RMS force.
+    full: the oracle's LJ force of every atom (so every atom is checked and F_rms is exact);
+    otherwise its LJ force of n_sample uniformly drawn atoms, which also estimate F_rms, plus the
+    50 atoms with the largest bonded force (checked, not used for F_rms).  Every bonded force
+    is checked either way."""
     f = s.forces()[:, atom_off:atom_off + melt.n_atoms]
     flj = s.forces(lj_only=True)[:, atom_off:atom_off + melt.n_atoms]
     fo_b, _ = O.bonded(ff, melt.pos, melt.box, melt.chain_len)
-    rng = np.random.default_rng(seed)
-    sample = rng.choice(melt.n_atoms, size=n_sample, replace=False)
-    if include_max:   # the atoms with the largest bonded force (forced contacts sit near them)
-        sample = np.unique(np.concatenate([sample, np.argsort(np.sum(fo_b ** 2, axis=0))[-50:]]))
-    fo_lj, _ = O.lj_cells(ff, melt.pos, melt.types, melt.box, melt.chain_len, subset=sample)
-    # each atom's error against its own total force (F_rms floor); the GPU total stands in for
-    # the oracle's where the oracle's LJ part is not computed (they agree to 1e-5)
-    err_lj = rel_err(flj[:, sample] - fo_lj, f[:, sample])
-    err_b = rel_err(f - flj - fo_b, f)
-    err = rel_err(f[:, sample] - fo_lj - fo_b[:, sample], fo_lj + fo_b[:, sample])
-    print("sampled force error (%d atoms): LJ %.3e bonded %.3e total %.3e" % (sample.size, err_lj, err_b, err))
+    if full:
+        fo_lj, _ = O.lj_cells(ff, melt.pos, melt.types, melt.box, melt.chain_len)
+        frms = rms(fo_lj + fo_b)
+        sample = np.arange(melt.n_atoms)
+    else:
+        rng = np.random.default_rng(seed)
+        uniform = rng.choice(melt.n_atoms, size=n_sample, replace=False)
+        top = np.argsort(np.sum(fo_b ** 2, axis=0))[-50:]   # forced contacts sit near them
+        sample = np.unique(np.concatenate([uniform, top]))
+        fo_lj, _ = O.lj_cells(ff, melt.pos, melt.types, melt.box, melt.chain_len, subset=sample)
+        pos_u = np.searchsorted(sample, uniform)
+        frms = rms(fo_lj[:, pos_u] + fo_b[:, uniform])
+    err_lj = norm_err(flj[:, sample] - fo_lj, frms)
+    err_b = norm_err(f - flj - fo_b, frms)
+    err = norm_err(f[:, sample] - fo_lj - fo_b[:, sample], frms)
+    print("force error over F_rms %.4f (%d atoms%s): LJ %.3e bonded %.3e total %.3e"
+          % (frms, sample.size, "" if full else ", sampled", err_lj, err_b, err), flush=True)
     assert err_lj <= TOL and err_b <= TOL and err <= TOL
 
 
@@ -87,7 +100,7 @@ def test_melt300k_bins_forces_energies(ff, melt300k):
     s = system(ff, [melt300k], WORKLOADS["melt300k_mixed"], cell_div=0, lj_kernel=0, use_graph=True)
     print("tuned (R, kernel) =", s.tuning(), flush=True)
     check_bins(s, melt300k)
-    check_sampled_forces(ff, s, melt300k, 4000, 17)
+    check_sampled_forces(ff, s, melt300k, 4000, 17)   # every atom (full)
     e = s.energies()[0]
     _, eo = O.lj_cells(ff, melt300k.pos, melt300k.types, melt300k.box, 300)
     _, eb = O.bonded(ff, melt300k.pos, melt300k.box, 300)
@@ -153,10 +166,12 @@ def test_melt300k_neighbour_lists_sampled_forces(ff, melt300k):
     s = system(ff, [melt300k], wl, cell_div=0, use_graph=True, nl_skin=1.0, nl_every=10)
     print("tuned (R, kernel) =", s.tuning(), flush=True)
     s.step(15)
+    s.energies()   # raises MDError if the device flagged the list (an atom past half the skin, a full list)
     pos, _ = s.state()
     s.compute_forces(True)
     cur = dataclasses.replace(melt300k, pos=pos)
     check_sampled_forces(ff, s, cur, 2000, 31)
+    s.energies()
     s.close()
 
 
@@ -202,7 +217,7 @@ def test_melt30M_bins_and_sampled_forces(ff):
     s = system(ff, [melt], WORKLOADS["melt30M_mixed"], cell_div=0, lj_kernel=0, use_graph=True)
     print("tuned (R, kernel) =", s.tuning(), flush=True)
     check_bins(s, melt)
-    check_sampled_forces(ff, s, melt, 1000, 29)
+    check_sampled_forces(ff, s, melt, 4000, 29, full=False)
     s.step(2)
     e = s.energies()[0]
     assert np.isfinite(e["temperature"]) and e["step"] == 2
@@ -224,8 +239,9 @@ def test_ensemble64_smallest_box(ff):
     off = sum(x.n_atoms for x in melts[:b])
     f = s.forces()[:, off:off + m.n_atoms]
     fo, eo = O.forces(ff, m.pos, m.types, m.box, m.chain_len)
-    print("smallest box %d (%d atoms): force error %.3e" % (b, m.n_atoms, rel_err(f - fo, fo)), flush=True)
-    assert rel_err(f - fo, fo) <= TOL
+    err = norm_err(f - fo, rms(fo))
+    print("smallest box %d (%d atoms): force error %.3e" % (b, m.n_atoms, err), flush=True)
+    assert err <= TOL
     energy_close(s.energies()[b], eo)
     s.step(100)
     p, v = s.state()
@@ -240,3 +256,16 @@ def test_ensemble64_smallest_box(ff):
           % (np.abs(d).max(), e100[b]["temperature"], eo100["temperature"]), flush=True)
     assert np.abs(d).max() <= 1e-4
     assert e100[b]["temperature"] == pytest.approx(eo100["temperature"], rel=1e-5)
+
+
+def test_melt300k_end_to_end_acf(ff, melt300k):
+    """The end-to-end autocorrelation of the 1,000 chains after 20 graph-replayed steps against
+    the oracle's, from the same positions (init is the reference)."""
+    s = system(ff, [melt300k], WORKLOADS["melt300k_mixed"], cell_div=0, lj_kernel=0, use_graph=True)
+    s.step(20)
+    p, _ = s.state()
+    got = s.ree_acf()[0]
+    want = O.ree_acf(melt300k.pos, p, melt300k.box, 300)
+    print("acf after 20 steps %.15f (oracle %.15f)" % (got, want), flush=True)
+    assert got == pytest.approx(want, rel=0, abs=1e-12) and abs(got - 1.0) < 0.05
+    s.close()

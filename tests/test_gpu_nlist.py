@@ -1,5 +1,6 @@
-"""Neighbour-list mode (the paper's Verlet list, rebuilt every few steps) against the FP64
-oracle and against the cell path, through the C ABI."""
+"""Neighbour-list mode (the paper's Verlet list, rebuilt when an atom has moved more than half
+the skin, or every few steps) against the FP64 oracle and against the cell path, through the
+C ABI."""
 import numpy as np
 import pytest
 
@@ -161,18 +162,81 @@ def test_nlist_batched_boxes(ff, kernel):
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
-def test_nlist_skin_exceeded_is_reported(ff, melt, kernel):
-    """A skin far too thin for the list's lifetime: the step reports MD_ERR_NLIST (the
-    device flags the displacement; nothing faults) and the context refuses further steps."""
-    from paper_1001_3764_amd.md import MD_ERR_NLIST, MD_ERR_STATE, MDError
+@pytest.mark.parametrize("precision,xtol", [("fp64", 1e-9), ("mixed", 1e-4)])
+def test_nlist_rebuilds_on_displacement(ff, melt, kernel, precision, xtol):
+    """Lists rebuilt only when an atom has moved more than half the skin (nl_every = 0), from the
+    500 K melt: 100 steps against the oracle's, which searches the cells every step, and the
+    graph-replayed and plain launch sequences bit-identical.  A 0.3 A skin makes the rebuilds
+    frequent but not every step."""
+    a = system(melt, ff, precision, 2, skin=0.3, every=0, kernel=kernel)
+    b = system(melt, ff, precision, 2, skin=0.3, every=0, kernel=kernel, use_graph=True)
+    f0, _ = O.forces(ff, melt.pos, melt.types, melt.box, 300)
+    a.step(100)
+    b.step(100)
+    pa, va = a.state()
+    pb, vb = b.state()
+    assert np.array_equal(pa, pb) and np.array_equal(va, vb)
+    a.energies()   # no device error
+    builds = a.list_builds()
+    assert b.list_builds() == builds
+    po, _, _, _ = O.run(ff, melt.pos, melt.vel, f0, melt.types, melt.box, 300, 100)
+    d = pa - po
+    d -= melt.box[:, None] * np.round(d / melt.box[:, None])
+    print("%s kernel %d: %d rebuilds in 100 steps, max|dx| %.3e A" % (precision, kernel, builds, np.abs(d).max()))
+    assert 3 <= builds < 100
+    assert np.abs(d).max() <= xtol
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_nlist_thin_skin_rebuilds_every_step_it_must(ff, melt, kernel):
+    """A skin far too thin for a fixed interval (0.02 A, nl_every = 100): the displacement check
+    rebuilds whenever an atom has crossed half of it, so the run follows the cell path (the same
+    pairs; only FP32 summation orders differ) and reports no error."""
     s = system(melt, ff, "mixed", 2, skin=0.02, every=100, kernel=kernel)
+    from paper_1001_3764_amd.md import MDSystem
+    c = MDSystem(ff, [melt.n_chains], melt.box[None, :], [0.0], melt.pos, melt.vel, melt.types,
+                 chain_len=melt.chain_len, precision="mixed", cell_div=2, lj_kernel=2)
     s.step(60)
-    with pytest.raises(MDError) as ex:
-        s.energies()
-    assert ex.value.status == MD_ERR_NLIST
-    with pytest.raises(MDError) as ex2:
-        s.step(1)
-    assert ex2.value.status == MD_ERR_STATE
+    c.step(60)
+    s.energies()
+    ps, _ = s.state()
+    pc, _ = c.state()
+    d = ps - pc
+    d -= melt.box[:, None] * np.round(d / melt.box[:, None])
+    builds = s.list_builds()
+    print("kernel %d: %d rebuilds in 60 steps, max|dx| vs cell path %.3e A" % (kernel, builds, np.abs(d).max()))
+    assert builds >= 30
+    assert np.abs(d).max() <= 1e-4
+    s.close()
+    c.close()
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_nlist_full_lists_fall_back_to_the_stencil(ff, melt, kernel, precision):
+    """The melt squeezed towards its box centre (positions scaled by 0.7 there): about 2.9 times
+    the mean density, so atoms and cells in the dense region have more list partners than the
+    capacity sized for the mean density holds.  Those walk their stencil instead; every force
+    still equals the oracle's."""
+    import dataclasses
+    L = melt.box[:, None]
+    p = L / 2 + 0.7 * (melt.pos - L / 2)
+    m = dataclasses.replace(melt, pos=p)
+    from scipy.spatial import cKDTree
+    rl = ff["rc"] + SKIN
+    counts = cKDTree(p.T, boxsize=melt.box).query_ball_point(p.T, rl, return_length=True)
+    mean = 4.0 / 3.0 * np.pi * rl ** 3 * melt.n_atoms / np.prod(melt.box)
+    assert counts.max() > 1.5 * mean + 64   # above the per-atom capacity for the mean density
+    s = system(m, ff, precision, 2, kernel=kernel)
+    flj = s.forces(lj_only=True)
+    fo_lj, eo = O.lj_cells(ff, m.pos, m.types, m.box, 300)
+    err = norm_err(flj, fo_lj)
+    print("squeezed melt %s kernel %d: LJ error %.3e (densest atom %d partners, mean %.0f)"
+          % (precision, kernel, err, counts.max(), mean))
+    assert err <= TOL[precision]
+    assert s.energies()[0]["e_lj"] == pytest.approx(eo["e_lj"], rel=1e-12 if precision == "fp64" else 2e-6)
     s.close()
 
 

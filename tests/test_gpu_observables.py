@@ -117,3 +117,41 @@ def test_observable_arguments_are_checked(ff, melt):
             s.observables(**kw)
         assert ex.value.status == MD_ERR_ARG
     s.close()
+
+
+def test_end_to_end_acf_against_the_oracle(ff):
+    """md_ree_acf against the oracle's ora_ree_acf: three boxes in one context, the reference at
+    init, then after 40 and 100 steps; then a new reference, 30 steps on.  Both sums are over
+    the same FP64 bond vectors in different orders, so they agree to rounding (1e-12)."""
+    from paper_1001_3764_amd.md import MDSystem
+    melts = [make_melt(c, density=0.80, T=450.0, seed_melt=700 + c, seed_vel=710 + c, jitter=0.05)
+             for c in (4, 9, 6)]
+    pos = np.concatenate([m.pos for m in melts], axis=1)
+    vel = np.concatenate([m.vel for m in melts], axis=1)
+    types = np.concatenate([m.types for m in melts])
+    s = MDSystem(ff, [m.n_chains for m in melts], np.stack([m.box for m in melts]), [0.0, 300.0, 0.0], pos, vel,
+                 types, precision="mixed", cell_div=2, lj_kernel=2, use_graph=True)
+    assert np.allclose(s.ree_acf(), 1.0, rtol=0, atol=1e-15)
+    ref = pos
+    for n in (40, 60):
+        s.step(n)
+        p, _ = s.state()
+        got = s.ree_acf()
+        off = 0
+        for b, m in enumerate(melts):
+            sl = slice(off, off + m.n_atoms)
+            want = O.ree_acf(ref[:, sl], p[:, sl], m.box, m.chain_len)
+            print("box %d: acf %.15f (oracle %.15f)" % (b, got[b], want), flush=True)
+            assert got[b] == pytest.approx(want, rel=0, abs=1e-12)
+            off += m.n_atoms
+    s.ree_reference()
+    ref, _ = s.state()
+    s.step(30)
+    p, _ = s.state()
+    got = s.ree_acf()
+    off = 0
+    for b, m in enumerate(melts):
+        sl = slice(off, off + m.n_atoms)
+        assert got[b] == pytest.approx(O.ree_acf(ref[:, sl], p[:, sl], m.box, m.chain_len), rel=0, abs=1e-12)
+        off += m.n_atoms
+    s.close()

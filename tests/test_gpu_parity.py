@@ -114,6 +114,91 @@ def test_forces_and_energies(ff, melt, precision, tol, R, kernel):
     s.close()
 
 
+def test_types_beyond_the_force_field_are_refused(ff, melt):
+    """Table I has two united atoms (types 0 and 1): a type 2 fails the set-up with MD_ERR_ARG."""
+    from paper_1001_3764_amd.md import MD_ERR_ARG, MDError
+    t = melt.types.copy()
+    t[1234] = 2
+    from paper_1001_3764_amd.md import MDSystem
+    with pytest.raises(MDError) as ex:
+        MDSystem(ff, [melt.n_chains], melt.box[None, :], [0.0], melt.pos, melt.vel, t, precision="mixed", cell_div=1)
+    assert ex.value.status == MD_ERR_ARG
+
+
+def forced_contacts(melt, targets, seed=5):
+    """A copy of the melt in which, for each target distance, one atom is moved towards a
+    nearby atom of another chain until the two are that far apart (minimum image), keeping every
+    other non-bonded distance of the moved atom above 2.8 A.  Returns the melt and the pairs."""
+    import dataclasses
+    from scipy.spatial import cKDTree
+    p = melt.pos.copy()
+    L = melt.box
+    rng = np.random.default_rng(seed)
+    pairs, used = [], set()
+    for r in targets:
+        for i in rng.permutation(melt.n_atoms):
+            tree = cKDTree(np.mod(p, L[:, None]).T, boxsize=L)
+            js = [j for j in tree.query_ball_point(np.mod(p[:, i], L), 5.0)
+                  if j // melt.chain_len != i // melt.chain_len and j not in used and i not in used]
+            if not js:
+                continue
+            j = js[0]
+            d = p[:, j] - p[:, i]
+            d -= L * np.round(d / L)
+            xj = p[:, i] + d * (r / np.linalg.norm(d))
+            near = tree.query_ball_point(np.mod(xj, L), 2.8)
+            others = [k for k in near if k not in (i, j) and (k // melt.chain_len != j // melt.chain_len
+                                                          or abs(k - j) > 3)]
+            if others:
+                continue
+            p[:, j] = np.mod(xj, L)
+            pairs.append((int(i), int(j), r))
+            used.update((int(i), int(j)))
+            break
+    assert len(pairs) == len(targets)
+    return dataclasses.replace(melt, pos=p), pairs
+
+
+CONTACTS = [1.9, 2.05, 2.2, 2.45, 2.58, 2.65]   # either side of 0.75 sigma = 2.6025 A
+
+
+@pytest.mark.parametrize("kernel,R,skin", [(1, 1, 0.0), (2, 1, 0.0), (2, 2, 0.0), (3, 2, 0.0), (6, 2, 0.0),
+                                           (4, 2, 1.0), (5, 2, 1.0)])
+def test_close_contacts_in_fp64(ff, melt, kernel, R, skin):
+    """Forced close contacts (1.9-2.65 A, LJ forces up to ~30 times the melt's RMS force): the mixed
+    form evaluates those below 0.75 sigma in FP64, so even there the error stays within 1e-5 of
+    the RMS force of the other atoms (FP32 alone errs by a few 1e-7 of the contact force, i.e.
+    several 1e-5 of it)."""
+    m, pairs = forced_contacts(melt, CONTACTS)
+    kw = dict(lj_kernel=kernel)
+    if skin:
+        kw.update(nl_skin=skin, nl_every=10)
+    s = make_system(m, ff, "mixed", R, **kw)
+    flj = s.forces(lj_only=True)
+    f = s.forces()
+    e = s.energies()[0]
+    fo_lj, eo = O.lj_cells(ff, m.pos, m.types, m.box, 300)
+    fo_b, eb = O.bonded(ff, m.pos, m.box, 300)
+    fo = fo_lj + fo_b
+    touched = np.array(sorted({a for i, j, _ in pairs for a in (i, j)}))
+    rest = np.setdiff1d(np.arange(m.n_atoms), touched)
+    frms_rest = np.sqrt(np.mean(np.sum(fo[:, rest] ** 2, axis=0)))
+    d_lj = np.sqrt(np.sum((flj - fo_lj) ** 2, axis=0))
+    print("contacts kernel=%d R=%d: |F| at contacts / F_rms(rest) up to %.1f; LJ error there %.3e, "
+          "elsewhere %.3e (over F_rms of the rest)"
+          % (kernel, R, np.sqrt(np.sum(fo[:, touched] ** 2, axis=0)).max() / frms_rest,
+             d_lj[touched].max() / frms_rest, d_lj[rest].max() / frms_rest), flush=True)
+    assert np.sqrt(np.sum(fo_lj[:, touched] ** 2, axis=0)).max() > 25 * frms_rest
+    # FP32 would err by ~1e-5 at the 1.9 A contact and ~5e-6 at 2.05 A
+    assert d_lj[touched].max() <= 3e-6 * frms_rest
+    assert d_lj.max() <= 1e-5 * frms_rest
+    assert norm_err(f, fo) <= TOL_MIXED
+    assert e["e_lj"] == pytest.approx(eo["e_lj"], rel=2e-6)
+    assert e["e_lj_shifted"] == pytest.approx(eo["e_lj_shifted"], rel=2e-6)
+    assert e["virial"] == pytest.approx(eo["virial_lj"] + eb["virial_bonded"], rel=2e-6)
+    s.close()
+
+
 @pytest.mark.parametrize("kernel", [1, 2, 6])
 @pytest.mark.parametrize("precision,xtol", [("fp64", 1e-9), ("mixed", 1e-4)])
 def test_trajectory_100_steps(ff, melt, precision, xtol, kernel):
@@ -260,15 +345,8 @@ def test_many_pairs_at_the_cutoff(ff, precision, R, kernel, nl):
     kw = dict(nl_skin=1.0, nl_every=5, lj_kernel=kernel) if nl else dict(lj_kernel=kernel)
     s = MDSystem(ff, [pos.shape[1] // 4], box[None, :], [0.0], pos, np.zeros_like(pos), types, chain_len=4,
                  precision=precision, cell_div=R, **kw)
-    if nl and kernel == 4:
-        # the list holds 1.5x the mean neighbour count of this sparse box plus 79 (80 entries):
-        # the centre's 100 partners overflow it, which is reported, not silently truncated
-        from paper_1001_3764_amd.md import MD_ERR_NLIST, MDError
-        with pytest.raises(MDError) as ex:
-            s.energies()
-        assert ex.value.status == MD_ERR_NLIST
-        s.close()
-        return
+    # per-atom lists (kernel 4) hold 1.5x the mean neighbour count of this sparse box plus 64:
+    # the centre's 100 partners overflow its list, so it walks its stencil instead
     flj = s.forces(lj_only=True)
     e = s.energies()[0]
     s.close()

@@ -178,3 +178,44 @@ def test_mass_weighted_rod(ff):
     c = (n - 1) / 2
     rg2 = b * b * (m * (n * (n * n - 1) / 12 - 2 * c * c) + 2 * M * c * c) / (m * (n - 2) + 2 * M)
     assert out[0, 0] == pytest.approx(rg2, rel=1e-12)
+
+
+def _rotate(u, axis, theta):
+    """Rodrigues rotation of the points u [3, n] about the unit axis through their first point."""
+    k = np.asarray(axis, dtype=float) / np.linalg.norm(axis)
+    p = u - u[:, :1]
+    c, s = math.cos(theta), math.sin(theta)
+    rot = p * c + np.cross(k, p.T).T * s + np.outer(k, k @ p) * (1.0 - c)
+    return rot + u[:, :1]
+
+
+def test_end_to_end_acf_closed_forms(melt3k):
+    """Fig. 8's end-to-end autocorrelation: 1 for the reference itself and after a rigid
+    translation (any wrap); cos(theta) when every chain is turned rigidly by theta about an axis
+    perpendicular to its end-to-end vector; -1 when every chain is point-reflected; and for
+    chains turned by different angles, the |R|^2-weighted mean of the cosines."""
+    from pe_melt import unwrap_chains
+    m = melt3k
+    L, n = m.box, m.chain_len
+    assert O.ree_acf(m.pos, m.pos, L, n) == pytest.approx(1.0, abs=1e-15)
+    shifted = np.mod(m.pos + np.array([[17.3], [-101.9], [4.4]]), L[:, None])
+    assert O.ree_acf(m.pos, shifted, L, n) == pytest.approx(1.0, abs=1e-13)
+    u = unwrap_chains(m.pos, L, n)
+    chains = [u[:, c * n:(c + 1) * n] for c in range(m.n_chains)]
+    ree = np.array([ch[:, -1] - ch[:, 0] for ch in chains])
+    rng = np.random.default_rng(3)
+
+    def turned(thetas):
+        out = []
+        for ch, r, th in zip(chains, ree, thetas):
+            axis = np.cross(r, rng.normal(size=3))       # perpendicular to this chain's R
+            out.append(_rotate(ch, axis, th))
+        return np.mod(np.concatenate(out, axis=1), L[:, None])
+
+    for theta in (0.3, 1.1, math.pi / 2, 2.5):
+        assert O.ree_acf(m.pos, turned([theta] * m.n_chains), L, n) == pytest.approx(math.cos(theta), abs=1e-12)
+    reflected = np.mod(np.concatenate([2 * ch[:, :1] - ch for ch in chains], axis=1), L[:, None])
+    assert O.ree_acf(m.pos, reflected, L, n) == pytest.approx(-1.0, abs=1e-13)
+    thetas = rng.uniform(0, math.pi, size=m.n_chains)
+    w = np.sum(ree ** 2, axis=1)
+    assert O.ree_acf(m.pos, turned(thetas), L, n) == pytest.approx(np.sum(w * np.cos(thetas)) / w.sum(), abs=1e-12)
