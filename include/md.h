@@ -154,6 +154,10 @@ typedef struct {
                                  T; translation only: a periodic box has no conserved rotation);
                                  the reported kinetic energy is then that of the motion relative
                                  to the centre of mass.  0: no removal */
+  int32_t tile_homes;         /* home atoms each wavefront of the mixed cell-tile kernels (2, 3, 5)
+                                 holds at a time against its stream of candidates: 4, 8 or 16;
+                                 0 = 8, or the autotuner's choice when it runs (cell_div = 0 or
+                                 lj_kernel = 0) */
 } md_config;
 
 /* Per-box results of the most recent energy evaluation. */
@@ -286,9 +290,10 @@ md_status md_forces(md_ctx* ctx, const void** f, int32_t* is_fp32);
 /* The Lennard-Jones part (Section 3.2, Eq. 2) of the force alone, same layout as md_forces. */
 md_status md_forces_lj(md_ctx* ctx, const void** f, int32_t* is_fp32);
 
-/* The cell size of Section 3.1 (edge >= rc / cell_div) and the LJ kernel in use (what the
-   autotuner chose, if asked).  Host only. */
-md_status md_tuning(const md_ctx* ctx, int32_t* cell_div, int32_t* lj_kernel);
+/* The cell size of Section 3.1 (edge >= rc / cell_div), the LJ kernel and the home atoms per
+   cell-tile wavefront in use (what the autotuner chose, if asked; tile_homes may be null).
+   Host only. */
+md_status md_tuning(const md_ctx* ctx, int32_t* cell_div, int32_t* lj_kernel, int32_t* tile_homes);
 
 /* Structural observables of Section 5 (Figs. 8-10, 12, 15). */
 #define MD_OBS_MAX_BINS 2048

@@ -24,6 +24,7 @@ struct md_ctx {
   double dt = 1.0, tau = 100.0;
   int prec = MD_PREC_MIXED;
   int R = 1, lj_kernel = MD_LJ_ATOM, use_graph = 0;
+  int homes = 8;             // home atoms per pass of a cell-tile wave (mixed precision)
   int64_t N = 0;
   FFDev ffd{};
   Views v{};
@@ -127,6 +128,10 @@ md_status validate(const md_forcefield* ff, const md_config* cfg, std::string* w
     return MD_ERR_ARG;
   }
   if (cfg->remove_com != 0 && cfg->remove_com != 1) { *why = "remove_com must be 0 or 1"; return MD_ERR_ARG; }
+  if (cfg->tile_homes != 0 && cfg->tile_homes != 4 && cfg->tile_homes != 8 && cfg->tile_homes != 16) {
+    *why = "tile_homes must be 0, 4, 8 or 16";
+    return MD_ERR_ARG;
+  }
   if (!(cfg->nl_skin >= 0.0) || !std::isfinite(cfg->nl_skin)) { *why = "nl_skin must be >= 0"; return MD_ERR_ARG; }
   if (cfg->nl_skin > 0.0 && cfg->nl_every < 0) { *why = "nl_every must be >= 0"; return MD_ERR_ARG; }
   if (cfg->nl_skin > 0.0 && cfg->cell_div > kTileMaxR) { *why = "neighbour lists need cell_div <= 2"; return MD_ERR_ARG; }
@@ -187,6 +192,8 @@ struct Plan {
   int64_t N = 0, C = 0;
   int32_t n_boxes = 0, n_atom_blocks = 0, n_lj_blocks = 0, n_tiles = 0;
   int32_t n_cell_blocks = 0, nl_cap = 0;   // neighbour-list mode
+  int32_t n_bd_chunks = 0, n_lj_chunks = 0, l1_bd = 0, l1_lj = 0;   // two-level reduction
+  std::vector<int32_t> chunk_rng;           // [2 * chunks] first and end partial
   int64_t nl_entries = 0;
   bool half = false;                        // half-shell LJ: fixed-point force accumulators
   int prec = 0;
@@ -275,6 +282,23 @@ Plan make_plan(const md_forcefield* ff, const md_config* cfg, int R, int kernel)
   p.n_atom_blocks = (int32_t)blk;
   p.n_lj_blocks = (int32_t)lblk;
   p.n_tiles = (int32_t)((cell + kScanTile - 1) / kScanTile);
+  // first-level chunks of the per-box reduction: bonded partials of every box, then LJ partials
+  for (int pass = 0; pass < 2; ++pass)
+    for (int b = 0; b < p.n_boxes; ++b) {
+      BoxDev& B = p.boxes[b];
+      const int32_t first = pass == 0 ? B.blk_off : B.lj_blk_off;
+      const int32_t end = pass == 0 ? (b + 1 < p.n_boxes ? p.boxes[b + 1].blk_off : p.n_atom_blocks)
+                                    : (b + 1 < p.n_boxes ? p.boxes[b + 1].lj_blk_off : p.n_lj_blocks);
+      const int32_t n = (end - first + kReduceChunk - 1) / kReduceChunk;
+      (pass == 0 ? B.bd_chunk_off : B.lj_chunk_off) = (int32_t)(p.chunk_rng.size() / 2);
+      (pass == 0 ? B.bd_chunks : B.lj_chunks) = n;
+      for (int32_t k = 0; k < n; ++k) {
+        p.chunk_rng.push_back(first + k * kReduceChunk);
+        p.chunk_rng.push_back(std::min(end, first + (k + 1) * kReduceChunk));
+      }
+      if (n > 1) (pass == 0 ? p.l1_bd : p.l1_lj) = 1;
+      (pass == 0 ? p.n_bd_chunks : p.n_lj_chunks) += n;
+    }
   return p;
 }
 
@@ -316,6 +340,12 @@ size_t carve(const Plan& p, char* base, Views* v) {
   t.err = (int32_t*)take(4);
   t.obs_part = (uint32_t*)take(4 * (size_t)kObsBlocks * kMaxObsBins);
   t.shift_tab = take((p.prec == MD_PREC_MIXED ? 12 : 24) * (size_t)kShiftSlots * p.n_boxes);
+  t.n_bd_chunks = p.n_bd_chunks;
+  t.n_lj_chunks = p.n_lj_chunks;
+  t.l1_bd = p.l1_bd;
+  t.l1_lj = p.l1_lj;
+  t.chunk_rng = (const int2*)take(4 * p.chunk_rng.size());
+  t.part_l1 = (dd*)take(sizeof(dd) * kBdParts * (size_t)(p.n_bd_chunks + p.n_lj_chunks));
   t.ree0 = (double*)take(24 * (size_t)(p.N / p.chain_len));
   t.ree_part = (double*)take(16 * (size_t)(p.N / p.chain_len));
   if (p.nl_cap) {
@@ -437,6 +467,9 @@ md_status configure(md_ctx* c, const md_config* cfg, int R, int kernel) {
       (st = hip_check(c, hipMemcpy((void*)v.cell_blk_box, cb.data(), 4 * cb.size(), hipMemcpyHostToDevice),
                       "upload list build block table")))
     return st;
+  if ((st = hip_check(c, hipMemcpy((void*)v.chunk_rng, p.chunk_rng.data(), 4 * p.chunk_rng.size(),
+                                   hipMemcpyHostToDevice), "upload reduction chunks")))
+    return st;
   if (R <= kTileMaxR) {
     // stencil shifts per box in the payload's units, and the sentinel slot
     const int W = 2 * R + 1;
@@ -507,9 +540,9 @@ BondedMode bonded_mode(const md_ctx* c, bool step) {
 void enqueue_forces(md_ctx* c, hipStream_t s, bool kick, bool energy) {
   const bool fp32 = c->prec == MD_PREC_MIXED;
   if (nl_mode(c))
-    launch_lj_nl(c->v, c->ffd, fp32, c->lj_kernel, energy, s);
+    launch_lj_nl(c->v, c->ffd, fp32, c->lj_kernel, energy, c->homes, s);
   else
-    launch_lj(c->v, c->ffd, fp32, c->lj_kernel, energy, s);
+    launch_lj(c->v, c->ffd, fp32, c->lj_kernel, energy, c->homes, s);
   launch_bonded(c->v, c->ffd, fp32, bonded_mode(c, kick), energy, kick && c->remove_com, c->dt, s);
 }
 
@@ -575,7 +608,7 @@ md_status capture_graphs(md_ctx* c) {
 constexpr float kTuneMargin = 0.03f;
 
 // Times rebuild + forces for each candidate and keeps the fastest (see kTuneMargin).
-md_status autotune(md_ctx* c, const md_config* cfg, int* bestR, int* bestK) {
+md_status autotune(md_ctx* c, const md_config* cfg, int* bestR, int* bestK, int* bestH) {
   std::vector<int> Rs, Ks;
   if (cfg->cell_div) Rs.push_back(cfg->cell_div);
   else
@@ -603,10 +636,23 @@ md_status autotune(md_ctx* c, const md_config* cfg, int* bestR, int* bestK) {
   float best = 1e30f;
   *bestR = Rs[0];
   *bestK = Ks[0];
+  *bestH = cfg->tile_homes ? cfg->tile_homes : 8;
+  // homes per wave of the mixed cell-tile kernels (atoms-per-wavefront): tuned unless given
+  const bool tile_tuned = cfg->precision == MD_PREC_MIXED && cfg->tile_homes == 0;
+  std::vector<std::pair<int, int>> KH;
+  for (int K : Ks) {
+    const bool tile = K == MD_LJ_CELLTILE || K == MD_LJ_CELLTILE_NB || K == MD_LJ_NLIST_TILE;
+    if (tile && tile_tuned)
+      for (int H : {4, 8, 16}) KH.push_back({K, H});
+    else
+      KH.push_back({K, *bestH});
+  }
   for (int R : Rs)
-    for (int K : Ks) {
-      if (Rs.size() * Ks.size() == 1) break;
+    for (auto kh : KH) {
+      const int K = kh.first;
+      if (Rs.size() * KH.size() == 1) break;
       if (K >= MD_LJ_CELLTILE && R > kTileMaxR) continue;
+      c->homes = kh.second;
       if ((st = configure(c, cfg, R, K))) break;
       enqueue_rebuild(c, c->stream, false);
       enqueue_forces(c, c->stream, false, false);
@@ -625,6 +671,7 @@ md_status autotune(md_ctx* c, const md_config* cfg, int* bestR, int* bestK) {
         best = ms;
         *bestR = R;
         *bestK = K;
+        *bestH = kh.second;
       }
     }
   (void)hipEventDestroy(e0);
@@ -740,7 +787,9 @@ static md_status init_impl(const md_forcefield* ff, const md_config* cfg, double
   local.T0 = c->T0.data();
   int R = cfg->cell_div ? cfg->cell_div : 1;
   int K = cfg->lj_kernel ? cfg->lj_kernel : MD_LJ_ATOM;
-  if (!cfg->cell_div || !cfg->lj_kernel) st = autotune(c, &local, &R, &K);
+  int H = cfg->tile_homes ? cfg->tile_homes : 8;
+  if (!cfg->cell_div || !cfg->lj_kernel) st = autotune(c, &local, &R, &K, &H);
+  c->homes = H;
   if (!st) st = configure(c, &local, R, K);
   if (!st) {
     enqueue_rebuild(c, c->stream, false);
@@ -876,9 +925,9 @@ md_status md_step_timed(md_ctx* c, int32_t n_steps, double* ms_out) {
     (void)hipEventRecord(e[15], s);
     (void)hipEventRecord(e[8], s);
     if (nl)
-      launch_lj_nl(c->v, c->ffd, fp32, c->lj_kernel, last, s);
+      launch_lj_nl(c->v, c->ffd, fp32, c->lj_kernel, last, c->homes, s);
     else
-      launch_lj(c->v, c->ffd, fp32, c->lj_kernel, last, s);
+      launch_lj(c->v, c->ffd, fp32, c->lj_kernel, last, c->homes, s);
     (void)hipEventRecord(e[9], s);
     (void)hipEventRecord(e[10], s);
     launch_bonded(c->v, c->ffd, fp32, bonded_mode(c, true), last, c->remove_com != 0, c->dt, s);
@@ -968,10 +1017,11 @@ md_status md_forces_lj(md_ctx* c, const void** f, int32_t* is_fp32) {
   return MD_OK;
 }
 
-md_status md_tuning(const md_ctx* c, int32_t* cell_div, int32_t* lj_kernel) {
+md_status md_tuning(const md_ctx* c, int32_t* cell_div, int32_t* lj_kernel, int32_t* tile_homes) {
   if (!c || !cell_div || !lj_kernel) return MD_ERR_ARG;
   *cell_div = c->R;
   *lj_kernel = c->lj_kernel;
+  if (tile_homes) *tile_homes = c->homes;
   return MD_OK;
 }
 

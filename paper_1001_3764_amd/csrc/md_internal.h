@@ -51,6 +51,9 @@ struct BoxDev {
   double dof;             // 3N - 3
   double inv_mass;        // 1 / total mass of the box
   int64_t nl_off;         // first entry of this box's neighbour lists
+  // first-level chunks of the per-box reduction (kReduceChunk block partials each)
+  int32_t bd_chunk_off, bd_chunks;   // of the bonded/kinetic partials
+  int32_t lj_chunk_off, lj_chunks;   // of the LJ partials (numbered after all bonded chunks)
 };
 
 // Force-field constants in the form the kernels use (built on the host).
@@ -160,6 +163,11 @@ struct Views {
   double nl_rl2;         // (rc + skin)^2
   double nl_half_skin2;  // (skin / 2)^2
   uint32_t* obs_part;    // [kObsBlocks * kMaxObsBins] block partials of the observables
+  // two-level per-box reduction (boxes with more than kReduceChunk block partials)
+  int32_t n_bd_chunks, n_lj_chunks;
+  int32_t l1_bd, l1_lj;  // 1: some box has more bonded / LJ partials than one chunk
+  const int2* chunk_rng; // [n_bd_chunks + n_lj_chunks] first and end partial of each chunk
+  dd* part_l1;           // [n_bd_chunks + n_lj_chunks][kBdParts] chunk sums
   const void* shift_tab;  // [n_boxes][kShiftSlots] stencil shifts in payload units (int32 x3 mixed, double x3
                           // FP64): slot code = the offset of stencil code, slot kSentinelCode the sentinel's
   double* ree0;          // [n_chains * 3] end-to-end vectors at the autocorrelation's reference time
@@ -169,6 +177,7 @@ struct Views {
 enum ErrBits : int32_t { kErrNonFinite = 1 };
 
 constexpr int kBdParts = 8;      // block partials of the bonded kernel
+constexpr int kReduceChunk = 2048;   // block partials one first-level reduction block sums
 constexpr int kMaxObsBins = 2048;  // histogram bins of one observable (md.h: MD_OBS_MAX_BINS)
 constexpr int kObsBlocks = 512;    // work-groups of an observable kernel (grid-stride)
 constexpr int kEnergySlots = 10; // per box: E_lj, E_lj_shifted, E_b, E_a, E_d, KE, T, W, xi, E_thermostat
@@ -227,14 +236,15 @@ void launch_ree(const Views& v, int b, int64_t n_chains, int chain_len, bool ref
 constexpr int kTileHomesMixed = 8;   // home atoms per pass of a mixed cell-tile wave
 
 // ---- launchers (md_lj.hip) ----
-void launch_lj(const Views& v, const FFDev& ff, bool fp32, int kernel, bool energy, hipStream_t s);
+// homes: home atoms per pass of a cell-tile wave (4, 8 or 16; mixed precision)
+void launch_lj(const Views& v, const FFDev& ff, bool fp32, int kernel, bool energy, int homes, hipStream_t s);
 int64_t lj_blocks_for_box(int kernel, int64_t n_atoms, int64_t n_cells);
 // neighbour-list mode: the list build (from the bins) and the LJ force from the list;
 // the force reads the current payload (pay_cur); gate: as for the bin kernels
 // kernel: MD_LJ_NLIST (per-atom lists) or MD_LJ_NLIST_TILE (per-cell lists)
 void launch_nl_build(const Views& v, const FFDev& ff, bool fp32, int kernel, hipStream_t s,
                      const int32_t* gate = nullptr);
-void launch_lj_nl(const Views& v, const FFDev& ff, bool fp32, int kernel, bool energy, hipStream_t s);
+void launch_lj_nl(const Views& v, const FFDev& ff, bool fp32, int kernel, bool energy, int homes, hipStream_t s);
 constexpr int kLjNlBlock = 256;   // threads per block of the list force kernel (box-aligned)
 constexpr int kTileWaves = 1;     // home cells (wavefronts) per block of the cell-tile kernels
 constexpr int kXcds = 8;          // accelerator complex dies of an MI355X (one L2 each)

@@ -652,8 +652,51 @@ __device__ void block_sums(dd (&s)[NV], dd (*sh)[NV]) {
   __syncthreads();
 }
 
+// First level of the per-box reduction for large boxes: block g sums one chunk of at most
+// kReduceChunk block partials (chunks [0, n_bd_chunks) hold bonded/kinetic partials, the rest
+// LJ partials), thread t adding partials t, t + 256, ... of the chunk in that order with their
+// loads in flight together, then the block in a fixed order.  The bonded sums are stored in
+// k_reduce's order (KE, [momentum xyz], [E_b E_a E_d W_b]), the LJ sums as E, E_shifted, W.
+template <bool ENERGY, bool COM>
+__global__ __launch_bounds__(256) void k_reduce_l1(Views v, int first_chunk) {
+  constexpr int iP = 1, iE = COM ? 4 : 1, NB = iE + (ENERGY ? 4 : 0);
+  constexpr int NQ = NB > 3 ? NB : 3;
+  constexpr int kPer = kReduceChunk / 256;
+  __shared__ dd sh[4][NQ];
+  const int g = first_chunk + (int)blockIdx.x;
+  const int2 rng = v.chunk_rng[g];
+  const bool bonded = g < v.n_bd_chunks;
+  dd q[NQ];
+  for (int k = 0; k < NQ; ++k) q[k] = dd{0.0, 0.0};
+  dd r[kPer][NQ];
+  const int64_t nb = v.n_atom_blocks;
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int j = min(rng.x + (int)threadIdx.x + 256 * u, rng.y - 1);   // past the end: re-read, not added
+    if (bonded) {
+      const dd* p = v.part_bd + j;
+      r[u][0] = p[4 * nb];
+      if (COM)
+        for (int k = 0; k < 3; ++k) r[u][iP + k] = p[(5 + k) * nb];
+      if (ENERGY)
+        for (int k = 0; k < 4; ++k) r[u][iE + k] = p[k * nb];
+    } else {
+      for (int k = 0; k < 3; ++k) r[u][k] = v.part_lj[(int64_t)j * 3 + k];
+    }
+  }
+  const int nq = bonded ? NB : 3;
+#pragma unroll
+  for (int u = 0; u < kPer; ++u)
+    if (rng.x + (int)threadIdx.x + 256 * u < rng.y)
+      for (int k = 0; k < nq; ++k) q[k] = dd_add(q[k], r[u][k]);
+  block_sums<NQ>(q, sh);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < nq; ++k) v.part_l1[(int64_t)g * kBdParts + k] = q[k];
+}
+
 // One block per box: the box's energies, kinetic energy and temperature, all partials read
-// in one pass; with update, the integrator state the next step applies:
+// in one pass (for large boxes, the first level's chunk sums, l1_bd / l1_lj); with update,
+// the integrator state the next step applies:
 //   velocity Verlet: the Berendsen factor lambda = sqrt(1 + dt/tau (T0/T - 1));
 //   leap-frog: xi' = xi + dt omega^2 (T/T0 - 1), omega = 2 pi / tau, eta += dt (xi + xi')/2,
 //              and the kick factors 1 - dt xi'/2 and 1 / (1 + dt xi'/2);
@@ -664,7 +707,7 @@ __device__ void block_sums(dd (&s)[NV], dd (*sh)[NV]) {
 // Neighbour-list mode, with update: the step's rebuild flag has been read by every kernel
 // that uses it, so it is counted and cleared here for the next step.
 template <bool ENERGY, bool COM>
-__global__ __launch_bounds__(256) void k_reduce(Views v, int update, StepOpts o) {
+__global__ __launch_bounds__(256) void k_reduce(Views v, int update, StepOpts o, int l1_bd, int l1_lj) {
   // q: KE, [momentum xyz], [E_b E_a E_d W_b E_lj E_lj_shifted W_lj]
   constexpr int iP = 1, iE = COM ? 4 : 1, NV = iE + (ENERGY ? 7 : 0);
   __shared__ dd sh[4][NV];
@@ -683,7 +726,11 @@ __global__ __launch_bounds__(256) void k_reduce(Views v, int update, StepOpts o)
   // a large box (117k partials at 30M atoms) waits for one round trip per batch, not per partial
   constexpr int NB = iE + (ENERGY ? 4 : 0);   // bonded partials read per work-group
   constexpr int kBatch = NB <= 4 ? 8 : 4;
-  for (int t0 = threadIdx.x; t0 < count; t0 += blockDim.x * kBatch) {
+  if (l1_bd) {
+    for (int t = threadIdx.x; t < B.bd_chunks; t += blockDim.x)
+      for (int k = 0; k < NB; ++k) q[k] = dd_add(q[k], v.part_l1[(int64_t)(B.bd_chunk_off + t) * kBdParts + k]);
+  }
+  for (int t0 = threadIdx.x; !l1_bd && t0 < count; t0 += blockDim.x * kBatch) {
     dd r[kBatch][NB];
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
@@ -702,10 +749,16 @@ __global__ __launch_bounds__(256) void k_reduce(Views v, int update, StepOpts o)
         for (int k = 0; k < NB; ++k) q[k] = dd_add(q[k], r[u][k]);
   }
   if (ENERGY) {
-    const int lfirst = B.lj_blk_off;
-    const int lcount = (b + 1 < v.n_boxes ? v.boxes[b + 1].lj_blk_off : v.n_lj_blocks) - lfirst;
-    for (int t = threadIdx.x; t < lcount; t += blockDim.x)
-      for (int k = 0; k < 3; ++k) q[iE + 4 + k] = dd_add(q[iE + 4 + k], v.part_lj[(int64_t)(lfirst + t) * 3 + k]);
+    if (l1_lj) {
+      for (int t = threadIdx.x; t < B.lj_chunks; t += blockDim.x)
+        for (int k = 0; k < 3; ++k)
+          q[iE + 4 + k] = dd_add(q[iE + 4 + k], v.part_l1[(int64_t)(B.lj_chunk_off + t) * kBdParts + k]);
+    } else {
+      const int lfirst = B.lj_blk_off;
+      const int lcount = (b + 1 < v.n_boxes ? v.boxes[b + 1].lj_blk_off : v.n_lj_blocks) - lfirst;
+      for (int t = threadIdx.x; t < lcount; t += blockDim.x)
+        for (int k = 0; k < 3; ++k) q[iE + 4 + k] = dd_add(q[iE + 4 + k], v.part_lj[(int64_t)(lfirst + t) * 3 + k]);
+    }
   }
   block_sums<NV>(q, sh);
   double KE = q[0].hi + q[0].lo;
@@ -869,15 +922,28 @@ void launch_bonded(const Views& v, const FFDev& ff, bool fp32, BondedMode mode, 
     launch_bonded_p<double>(v, ff, mode, energy, com, dt, s);
 }
 
+// Large boxes go through the first-level chunk sums: the bonded chunks when some box has more
+// than kReduceChunk atom blocks, the LJ chunks (energy evaluations only) when some box has more
+// than kReduceChunk LJ blocks.
 void launch_reduce(const Views& v, bool energy, bool update, const StepOpts& o, hipStream_t s) {
   const int u = update ? 1 : 0;
   const bool com = update && o.remove_com;
+  const int l1_bd = v.l1_bd, l1_lj = energy && v.l1_lj ? 1 : 0;
+  if (l1_bd || l1_lj) {
+    const int c0 = l1_bd ? 0 : v.n_bd_chunks;
+    const int c1 = l1_lj ? v.n_bd_chunks + v.n_lj_chunks : v.n_bd_chunks;
+    const dim3 g(c1 - c0), blk(256);
+#define MDK_L1(E, C) hipLaunchKernelGGL((k_reduce_l1<E, C>), g, blk, 0, s, v, c0)
+    if (energy) { if (com) MDK_L1(true, true); else MDK_L1(true, false); }
+    else { if (com) MDK_L1(false, true); else MDK_L1(false, false); }
+#undef MDK_L1
+  }
   if (energy) {
-    if (com) hipLaunchKernelGGL((k_reduce<true, true>), dim3(v.n_boxes), dim3(256), 0, s, v, u, o);
-    else hipLaunchKernelGGL((k_reduce<true, false>), dim3(v.n_boxes), dim3(256), 0, s, v, u, o);
+    if (com) hipLaunchKernelGGL((k_reduce<true, true>), dim3(v.n_boxes), dim3(256), 0, s, v, u, o, l1_bd, l1_lj);
+    else hipLaunchKernelGGL((k_reduce<true, false>), dim3(v.n_boxes), dim3(256), 0, s, v, u, o, l1_bd, l1_lj);
   } else {
-    if (com) hipLaunchKernelGGL((k_reduce<false, true>), dim3(v.n_boxes), dim3(256), 0, s, v, u, o);
-    else hipLaunchKernelGGL((k_reduce<false, false>), dim3(v.n_boxes), dim3(256), 0, s, v, u, o);
+    if (com) hipLaunchKernelGGL((k_reduce<false, true>), dim3(v.n_boxes), dim3(256), 0, s, v, u, o, l1_bd, l1_lj);
+    else hipLaunchKernelGGL((k_reduce<false, false>), dim3(v.n_boxes), dim3(256), 0, s, v, u, o, l1_bd, l1_lj);
   }
 }
 

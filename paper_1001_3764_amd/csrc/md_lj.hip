@@ -726,19 +726,63 @@ __device__ __forceinline__ BandEnergy settle_group(const Views& v, int chain_len
   return BandEnergy{e, es, w};
 }
 
+// Sums KMAX per-lane force accumulators (three components each) over the 64 lanes in a
+// fixed order.  Recursive halving: at each of the first log2(KMAX) levels a lane keeps half of
+// its values and adds the partner's copy of that half, so the 3 KMAX sums take 3 KMAX - 3
+// exchanges (instead of 18 KMAX for separate butterflies); then a butterfly over the remaining
+// lane bits.  Level lv splits the lanes by bit 5 - lv and exchanges through kLevel[lv] (for
+// bit 2 the partner l ^ 7 also differs in bit 2 only among the bits not yet summed).
+// Afterwards every lane of [h * 64/KMAX, (h + 1) * 64/KMAX) holds accumulator h's sums.
+template <typename P, int KMAX>
+__device__ __forceinline__ void sum_homes(int ln, P (&ax)[KMAX], P (&ay)[KMAX], P (&az)[KMAX], P& sx, P& sy,
+                                          P& sz) {
+  constexpr int LV = KMAX == 16 ? 4 : (KMAX == 8 ? 3 : (KMAX == 4 ? 2 : (KMAX == 2 ? 1 : 0)));
+  static_assert((1 << LV) == KMAX, "KMAX must be 1, 2, 4, 8 or 16");
+  constexpr int NV = 3 * KMAX;
+  P val[NV];
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    val[3 * k] = ax[k];
+    val[3 * k + 1] = ay[k];
+    val[3 * k + 2] = az[k];
+  }
+#pragma unroll
+  for (int lv = 0; lv < LV; ++lv) {
+#pragma unroll
+    for (int i = 0; i < (NV >> lv) / 2; ++i) {
+      const int h = (NV >> lv) / 2 + i;
+      if (lv < 2) {
+        // lanes below the split keep val[i], those above val[h]
+        val[i] = swap_sum(val[i], val[h], kLevel[lv]);
+      } else {
+        const bool hi = (ln & (32 >> lv)) != 0;
+        const P send = hi ? val[i] : val[h];
+        const P keep = hi ? val[h] : val[i];
+        val[i] = keep + partner(send, lv == 2 ? Xl::Ror8 : Xl::Mirror8);
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) val[c] = group_sum(val[c], LV);
+  sx = val[0];
+  sy = val[1];
+  sz = val[2];
+}
+
 // Occupancy targets (measured): the mixed form is held to 6 waves per SIMD (80 VGPRs; left
 // alone the compiler takes 82 and runs 5, and the few values it then spills sit outside the
 // pair loop: 8% faster); the FP64 form (K = 4) fits 8.
 // LIST: neighbour-list mode with per-cell lists (the homes and the sorted order are those of
 // the last build, the payload the one refreshed since).
 template <bool FP64, bool ENERGY, bool UNI, int KMAX, bool BRANCHLESS, bool LIST = false>
-__global__ __launch_bounds__(64 * kTileWaves) __attribute__((amdgpu_waves_per_eu(FP64 ? 8 : 6)))
+__global__ __launch_bounds__(64 * kTileWaves)
+__attribute__((amdgpu_waves_per_eu(FP64 ? 8 : (KMAX >= 16 ? 4 : (KMAX <= 4 ? 8 : 6)))))
 void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
   using PayT = std::conditional_t<FP64, Pay64, int4>;
   using P = std::conditional_t<FP64, double, float>;
   using Q = std::conditional_t<FP64, double, int>;     // coordinate type
-  constexpr int LV = KMAX == 8 ? 3 : (KMAX == 4 ? 2 : (KMAX == 2 ? 1 : 0));   // log2(KMAX)
-  static_assert((1 << LV) == KMAX, "KMAX must be 1, 2, 4 or 8");
+  constexpr int LV = KMAX == 16 ? 4 : (KMAX == 8 ? 3 : (KMAX == 4 ? 2 : (KMAX == 2 ? 1 : 0)));   // log2(KMAX)
+  static_assert((1 << LV) == KMAX, "KMAX must be 1, 2, 4, 8 or 16");
   __shared__ uint32_t list[kTileWaves][kListCap + 65];   // + the padding to a whole step, + 1
   __shared__ Shift<Q> shifts[kShiftSlots];
   __shared__ dd red[kTileWaves][3];
@@ -914,12 +958,10 @@ void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
           }
         }
       }
-      // Sum each home atom's partial forces over the 64 lanes in a fixed order.  Recursive
-      // halving: at each of the first log2(KMAX) levels a lane keeps half of its values and
-      // adds the partner's copy of that half, so the 3 KMAX sums take 3 KMAX - 3 exchanges
-      // (instead of 18 KMAX for separate butterflies); then a butterfly over the remaining
-      // lane bits, after which lanes [h * 64/KMAX, (h + 1) * 64/KMAX) hold home h's sums
-      // and the first of them stores it (and later applies its band corrections).
+      // Sum each home atom's partial forces over the 64 lanes in a fixed order, as sum_homes
+      // does (written out here: the explicit exchange patterns keep the register allocation
+      // tighter): lanes [h * 64/KMAX, (h + 1) * 64/KMAX) then hold home h's sums, and the first
+      // of them stores it (and later applies its band and close-contact corrections).
       P* f = static_cast<P*>(v.f_lj);
       {
         constexpr int NV = 3 * KMAX;
@@ -936,13 +978,12 @@ void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
           for (int i = 0; i < (NV >> lv) / 2; ++i) {
             const int h = (NV >> lv) / 2 + i;
             if (lv < 2) {
-              // lanes below the split keep val[i], those above val[h]
               val[i] = swap_sum(val[i], val[h], kLevel[lv]);
             } else {
-              const bool hi = (ln & 8) != 0;
+              const bool hi = (ln & (32 >> lv)) != 0;
               const P send = hi ? val[i] : val[h];
               const P keep = hi ? val[h] : val[i];
-              val[i] = keep + partner(send, Xl::Ror8);
+              val[i] = keep + partner(send, lv == 2 ? Xl::Ror8 : Xl::Mirror8);
             }
           }
         }
@@ -977,45 +1018,6 @@ void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
     }
   }
   if (ENERGY) block_energy<kTileWaves>(e, es, w, red, v.part_lj + (int64_t)blk * 3);
-}
-
-// Sums KMAX per-lane force accumulators (three components each) over the 64 lanes in a
-// fixed order, as the cell tile does inline: recursive halving over the first log2(KMAX) lane
-// bits, then a butterfly over the rest.  Afterwards every lane of
-// [h * 64/KMAX, (h + 1) * 64/KMAX) holds accumulator h's sums.
-template <typename P, int KMAX>
-__device__ __forceinline__ void sum_homes(int ln, P (&ax)[KMAX], P (&ay)[KMAX], P (&az)[KMAX], P& sx, P& sy,
-                                          P& sz) {
-  constexpr int LV = KMAX == 8 ? 3 : (KMAX == 4 ? 2 : (KMAX == 2 ? 1 : 0));
-  static_assert((1 << LV) == KMAX, "KMAX must be 1, 2, 4 or 8");
-  constexpr int NV = 3 * KMAX;
-  P val[NV];
-#pragma unroll
-  for (int k = 0; k < KMAX; ++k) {
-    val[3 * k] = ax[k];
-    val[3 * k + 1] = ay[k];
-    val[3 * k + 2] = az[k];
-  }
-#pragma unroll
-  for (int lv = 0; lv < LV; ++lv) {
-#pragma unroll
-    for (int i = 0; i < (NV >> lv) / 2; ++i) {
-      const int h = (NV >> lv) / 2 + i;
-      if (lv < 2) {
-        val[i] = swap_sum(val[i], val[h], kLevel[lv]);
-      } else {
-        const bool hi = (ln & 8) != 0;
-        const P send = hi ? val[i] : val[h];
-        const P keep = hi ? val[h] : val[i];
-        val[i] = keep + partner(send, Xl::Ror8);
-      }
-    }
-  }
-#pragma unroll
-  for (int c = 0; c < 3; ++c) val[c] = group_sum(val[c], LV);
-  sx = val[0];
-  sy = val[1];
-  sz = val[2];
 }
 
 // ---------------------------------------------------------------------------------
@@ -1607,11 +1609,10 @@ LjPair<P> make_pair(const FFDev& ff) {
   return c;
 }
 
-template <bool FP64, bool ENERGY, bool LIST = false>
-void launch_tile(const Views& v, const FFDev& ff, const LjPair<float>& cf, const LjPair<double>& cd,
-                 bool branchless, hipStream_t s) {
+template <bool FP64, bool ENERGY, int K, bool LIST>
+void launch_tile_k(const Views& v, const FFDev& ff, const LjPair<float>& cf, const LjPair<double>& cd,
+                   bool branchless, hipStream_t s) {
   dim3 g((v.n_lj_blocks + kXcds - 1) / kXcds * kXcds), b(64 * kTileWaves);
-  constexpr int K = FP64 ? 4 : kTileHomesMixed;
   if (ff.uniform_lj) {
     if (branchless && !LIST)
       hipLaunchKernelGGL((k_lj_tile<FP64, ENERGY, true, K, true>), g, b, 0, s, v, ff, cf, cd);
@@ -1620,6 +1621,18 @@ void launch_tile(const Views& v, const FFDev& ff, const LjPair<float>& cf, const
   } else {
     hipLaunchKernelGGL((k_lj_tile<FP64, ENERGY, false, K, false, LIST>), g, b, 0, s, v, ff, cf, cd);
   }
+}
+
+// homes: home atoms per pass of a wave (4, 8 or 16; the FP64 form holds 4 in scalar registers).
+template <bool FP64, bool ENERGY, bool LIST = false>
+void launch_tile(const Views& v, const FFDev& ff, const LjPair<float>& cf, const LjPair<double>& cd,
+                 bool branchless, int homes, hipStream_t s) {
+  if (FP64 || homes == 4)
+    launch_tile_k<FP64, ENERGY, 4, LIST>(v, ff, cf, cd, branchless, s);
+  else if (homes == 16)
+    launch_tile_k<FP64, ENERGY, 16, LIST>(v, ff, cf, cd, branchless, s);
+  else
+    launch_tile_k<FP64, ENERGY, 8, LIST>(v, ff, cf, cd, branchless, s);
 }
 
 }  // namespace
@@ -1646,7 +1659,7 @@ void launch_nl_build(const Views& v, const FFDev& ff, bool fp32, int kernel, hip
 }
 
 // Neighbour-list forces always read the current payload (the build's right after a rebuild).
-void launch_lj_nl(const Views& v, const FFDev& ff, bool fp32, int kernel, bool energy, hipStream_t s) {
+void launch_lj_nl(const Views& v, const FFDev& ff, bool fp32, int kernel, bool energy, int homes, hipStream_t s) {
   const LjPair<float> cf = make_pair<float>(ff);
   const LjPair<double> cd = make_pair<double>(ff);
   const void* pay = v.pay_cur;
@@ -1654,11 +1667,11 @@ void launch_lj_nl(const Views& v, const FFDev& ff, bool fp32, int kernel, bool e
     Views w = v;
     w.payload = const_cast<void*>(pay);
     if (fp32) {
-      if (energy) launch_tile<false, true, true>(w, ff, cf, cd, false, s);
-      else launch_tile<false, false, true>(w, ff, cf, cd, false, s);
+      if (energy) launch_tile<false, true, true>(w, ff, cf, cd, false, homes, s);
+      else launch_tile<false, false, true>(w, ff, cf, cd, false, homes, s);
     } else {
-      if (energy) launch_tile<true, true, true>(w, ff, cf, cd, false, s);
-      else launch_tile<true, false, true>(w, ff, cf, cd, false, s);
+      if (energy) launch_tile<true, true, true>(w, ff, cf, cd, false, homes, s);
+      else launch_tile<true, false, true>(w, ff, cf, cd, false, homes, s);
     }
     return;
   }
@@ -1674,7 +1687,7 @@ void launch_lj_nl(const Views& v, const FFDev& ff, bool fp32, int kernel, bool e
 #undef MDK_NL
 }
 
-void launch_lj(const Views& v, const FFDev& ff, bool fp32, int kernel, bool energy, hipStream_t s) {
+void launch_lj(const Views& v, const FFDev& ff, bool fp32, int kernel, bool energy, int homes, hipStream_t s) {
   const LjPair<float> cf = make_pair<float>(ff);
   const LjPair<double> cd = make_pair<double>(ff);
   if (kernel == 6) {
@@ -1694,11 +1707,11 @@ void launch_lj(const Views& v, const FFDev& ff, bool fp32, int kernel, bool ener
   if (kernel == 2 || kernel == 3) {
     const bool bl = kernel == 3 && fp32;
     if (fp32) {
-      if (energy) launch_tile<false, true>(v, ff, cf, cd, bl, s);
-      else launch_tile<false, false>(v, ff, cf, cd, bl, s);
+      if (energy) launch_tile<false, true>(v, ff, cf, cd, bl, homes, s);
+      else launch_tile<false, false>(v, ff, cf, cd, bl, homes, s);
     } else {
-      if (energy) launch_tile<true, true>(v, ff, cf, cd, bl, s);
-      else launch_tile<true, false>(v, ff, cf, cd, bl, s);
+      if (energy) launch_tile<true, true>(v, ff, cf, cd, bl, homes, s);
+      else launch_tile<true, false>(v, ff, cf, cd, bl, homes, s);
     }
     return;
   }

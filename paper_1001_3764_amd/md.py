@@ -36,7 +36,8 @@ class md_config(ctypes.Structure):
     _fields_ = [("n_boxes", _I32), ("chain_len", _I32), ("n_chains", ctypes.POINTER(_I32)),
                 ("box", ctypes.POINTER(_D)), ("T0", ctypes.POINTER(_D)), ("dt_fs", _D), ("tau_fs", _D),
                 ("precision", _I32), ("cell_div", _I32), ("lj_kernel", _I32), ("use_graph", _I32),
-                ("nl_skin", _D), ("nl_every", _I32), ("integrator", _I32), ("remove_com", _I32)]
+                ("nl_skin", _D), ("nl_every", _I32), ("integrator", _I32), ("remove_com", _I32),
+                ("tile_homes", _I32)]
 
 
 class md_energy(ctypes.Structure):
@@ -87,7 +88,7 @@ def load():
         "md_grid": (S, [_P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
         "md_forces": (S, [_P, ctypes.POINTER(_P), ctypes.POINTER(_I32)]),
         "md_forces_lj": (S, [_P, ctypes.POINTER(_P), ctypes.POINTER(_I32)]),
-        "md_tuning": (S, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+        "md_tuning": (S, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
         "md_destroy": (S, [_P]),
         "md_observables": (S, [_P, _P, _P, _P, _P]),
         "md_ree_reference": (S, [_P]),
@@ -135,7 +136,7 @@ class _Config:
     """md_config plus the host arrays it points to (kept alive together)."""
 
     def __init__(self, n_chains, boxes, T0, chain_len, dt, tau, precision, cell_div, lj_kernel, use_graph,
-                 nl_skin=0.0, nl_every=1, integrator=MD_INT_VERLET_BERENDSEN, remove_com=False):
+                 nl_skin=0.0, nl_every=1, integrator=MD_INT_VERLET_BERENDSEN, remove_com=False, tile_homes=0):
         self.n_chains = np.ascontiguousarray(n_chains, dtype=np.int32)
         self.box = np.ascontiguousarray(np.asarray(boxes, dtype=np.float64).reshape(-1, 3))
         self.T0 = np.ascontiguousarray(T0, dtype=np.float64)
@@ -155,6 +156,7 @@ class _Config:
         c.nl_every = int(nl_every)
         c.integrator = int(integrator)
         c.remove_com = int(bool(remove_com))
+        c.tile_homes = int(tile_homes)
         self.c = c
 
 
@@ -235,10 +237,11 @@ def md_forces_lj(ctx):
     return f.value, bool(fp32.value)
 
 
-def md_tuning(ctx):
-    r, k = _I32(), _I32()
-    _check(load().md_tuning(ctx, ctypes.byref(r), ctypes.byref(k)), "md_tuning", ctx)
-    return r.value, k.value
+def md_tuning(ctx, homes=False):
+    """(cell_div, lj_kernel), or (cell_div, lj_kernel, tile_homes) with homes=True."""
+    r, k, h = _I32(), _I32(), _I32()
+    _check(load().md_tuning(ctx, ctypes.byref(r), ctypes.byref(k), ctypes.byref(h)), "md_tuning", ctx)
+    return (r.value, k.value, h.value) if homes else (r.value, k.value)
 
 
 def md_ree_reference(ctx):
@@ -280,7 +283,8 @@ class MDSystem:
 
     def __init__(self, ff: dict, n_chains, boxes, T0, pos, vel, types, chain_len=300, dt=1.0, tau=100.0,
                  precision="mixed", cell_div=1, lj_kernel=None, use_graph=False, device="cuda:0",
-                 nl_skin=0.0, nl_every=10, integrator="verlet", remove_com=False, static_workspace=False):
+                 nl_skin=0.0, nl_every=10, integrator="verlet", remove_com=False, static_workspace=False,
+                 tile_homes=0):
         """lj_kernel: an md_lj_kernel; None is MD_LJ_ATOM on the cell path and the autotuner
         (0) in neighbour-list mode.
         static_workspace: set up with md_init_system_static (the library's own device array as
@@ -296,7 +300,7 @@ class MDSystem:
         if lj_kernel is None:
             lj_kernel = MD_LJ_AUTO if nl_skin > 0 else MD_LJ_ATOM
         self.cfg = _Config(n_chains, boxes, T0, chain_len, dt, tau, precision, cell_div, lj_kernel, use_graph,
-                           nl_skin, nl_every, integ, remove_com)
+                           nl_skin, nl_every, integ, remove_com, tile_homes)
         self.n_boxes = self.cfg.c.n_boxes
         pos = np.ascontiguousarray(pos, dtype=np.float64)
         vel = np.ascontiguousarray(vel, dtype=np.float64)
@@ -334,8 +338,8 @@ class MDSystem:
     def energies(self):
         return md_energies(self.ctx, self.n_boxes)
 
-    def tuning(self):
-        return md_tuning(self.ctx)
+    def tuning(self, homes=False):
+        return md_tuning(self.ctx, homes)
 
     def list_builds(self):
         return md_list_builds(self.ctx)

@@ -114,6 +114,33 @@ def test_forces_and_energies(ff, melt, precision, tol, R, kernel):
     s.close()
 
 
+@pytest.mark.parametrize("homes", [4, 8, 16])
+@pytest.mark.parametrize("kernel,R,skin", [(2, 1, 0.0), (2, 2, 0.0), (3, 2, 0.0), (5, 2, 1.0)])
+def test_tile_homes_per_wave(ff, melt, homes, kernel, R, skin):
+    """The cell tile with 4, 8 or 16 home atoms per pass of a wavefront (the autotuner's
+    atoms-per-wave choice): forces, energies and a 50-step trajectory against the oracle; the
+    choice is reported back by md_tuning."""
+    kw = dict(lj_kernel=kernel, tile_homes=homes)
+    if skin:
+        kw.update(nl_skin=skin, nl_every=0)
+    s = make_system(melt, ff, "mixed", R, **kw)
+    assert s.tuning(homes=True) == (R, kernel, homes)
+    f = s.forces()
+    e = s.energies()[0]
+    fo, eo = O.forces(ff, melt.pos, melt.types, melt.box, 300)
+    err = norm_err(f, fo)
+    print("homes=%d kernel=%d R=%d: force error %.3e" % (homes, kernel, R, err), flush=True)
+    assert err <= TOL_MIXED
+    assert e["e_lj"] == pytest.approx(eo["e_lj"], rel=2e-6)
+    s.step(50)
+    p, _ = s.state()
+    po, _, _, _ = O.run(ff, melt.pos, melt.vel, fo, melt.types, melt.box, 300, 50)
+    d = p - po
+    d -= melt.box[:, None] * np.round(d / melt.box[:, None])
+    assert np.abs(d).max() <= 1e-4
+    s.close()
+
+
 def test_types_beyond_the_force_field_are_refused(ff, melt):
     """Table I has two united atoms (types 0 and 1): a type 2 fails the set-up with MD_ERR_ARG."""
     from paper_1001_3764_amd.md import MD_ERR_ARG, MDError
