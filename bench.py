@@ -178,6 +178,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--fp64-steps", type=int, default=200, help="FP64 steps of the other workloads")
+    ap.add_argument("--relax-steps", type=int, default=500,
+                    help="steps of the mixed form that relax each grown melt before anything is timed")
     ap.add_argument("--cell-div", type=int, default=0, help="0 = autotune")
     ap.add_argument("--lj-kernel", type=int, default=0, help="0 = autotune")
     ap.add_argument("--no-graph", action="store_true")
@@ -226,15 +228,23 @@ def main():
         torch.cuda.synchronize(dev)
         del src, dst
 
-    # ---- mixed precision, graph-replayed: the headline ----
-    s = MDSystem(ff, [melt.n_chains], melt.box[None, :], [wl.T0[0]], melt.pos, melt.vel, melt.types,
-                 chain_len=wl.chain_len, dt=wl.dt_fs, tau=wl.tau_fs, precision="mixed",
-                 cell_div=args.cell_div, lj_kernel=args.lj_kernel, use_graph=not args.no_graph, device=dev)
-    R, kern = s.tuning()
-    log("mixed: cell_div R=%d, lj kernel %d" % (R, kern))
+    def mixed_system(pos, vel):
+        return MDSystem(ff, [melt.n_chains], melt.box[None, :], [wl.T0[0]], pos, vel, melt.types,
+                        chain_len=wl.chain_len, dt=wl.dt_fs, tau=wl.tau_fs, precision="mixed",
+                        cell_div=args.cell_div, lj_kernel=args.lj_kernel, use_graph=not args.no_graph, device=dev)
+
+    # ---- the input: the grown melt (its forces checked against the oracle below), relaxed by
+    # relax_steps steps of the mixed form toward T0; every timed form starts from that state ----
+    s = mixed_system(melt.pos, melt.vel)
     f_mixed = s.forces()
     f_mixed_lj = s.forces(lj_only=True)
-    start0, _ = s.bins()
+    p_start, v_start, grown = relax_input(s, args.relax_steps, N, dev)
+    s.close()
+
+    # ---- mixed precision, graph-replayed: the headline ----
+    s = mixed_system(p_start, v_start)
+    R, kern = s.tuning()
+    log("mixed: cell_div R=%d, lj kernel %d" % (R, kern))
     M, _, _ = s.grid(0)
     s.step(args.warmup)
     torch.cuda.synchronize(dev)
@@ -415,14 +425,13 @@ def main():
     except Exception as exc:   # the metric line is still printed
         log("force error check failed: %r" % (exc,))
 
-    # ---- plain FP64 GPU form: FP64 everywhere, no graph, its own autotuned grid/kernel ----
     # ---- plain FP64 GPU form (FP64 everywhere, no graph, its own autotuned grid and kernel): the
-    # same warm-up and timed steps from the same grown melt; and the same FP64 form graph-replayed,
+    # same warm-up and timed steps from the same relaxed melt; and the same FP64 form graph-replayed,
     # to separate the effect of precision from that of the saved launches ----
     plain = plain_graph = None
     if not args.no_fp64:
         for graph in (False, True):
-            s64 = MDSystem(ff, [melt.n_chains], melt.box[None, :], [wl.T0[0]], melt.pos, melt.vel, melt.types,
+            s64 = MDSystem(ff, [melt.n_chains], melt.box[None, :], [wl.T0[0]], p_start, v_start, melt.types,
                            chain_len=wl.chain_len, dt=wl.dt_fs, tau=wl.tau_fs, precision="fp64", cell_div=0,
                            lj_kernel=0, use_graph=graph, device=dev)
             R64, k64 = s64.tuning()
@@ -476,7 +485,9 @@ def main():
                    "T_init_K": wl.T_init[0], "T0_K": wl.T0[0], "thermostat": "berendsen",
                    "tau_fs": wl.tau_fs, "dt_fs": wl.dt_fs, "precision": "mixed (FP32 force, FP64 state)",
                    "cell_div": R, "cells_per_dim": [int(x) for x in M], "lj_kernel": kern,
-                   "graph": not args.no_graph, "bins_rebuilt_every_step": True},
+                   "graph": not args.no_graph, "bins_rebuilt_every_step": True,
+                   "relax_steps": args.relax_steps},
+        "grown_melt_first_steps": grown,
         "ns_per_day": (1e3 / ms_per_step) * wl.dt_fs * 86400 * 1e-6,
         "force_err_vs_fp64_oracle": force_err,
         "plain_fp64_gpu": plain,
@@ -514,6 +525,26 @@ def _concat(melts):
             [m.n_chains for m in melts])
 
 
+def relax_input(s, steps, n_atoms, dev):
+    """Relaxes a grown melt: `steps` steps of system s (the grown configuration has close
+    contacts that the first few hundred femtoseconds push apart, and it starts above T0).
+    Returns the relaxed positions and velocities and the rate of those first steps (None for
+    steps = 0)."""
+    import torch
+    if steps <= 0:
+        p, v = s.state()
+        return p, v, None
+    torch.cuda.synchronize(dev)
+    a = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize(dev)
+    wall = time.perf_counter() - a
+    p, v = s.state()
+    log("relaxed the grown melt: %d steps, %.3f ms/step" % (steps, 1e3 * wall / steps))
+    return p, v, {"steps": steps, "ms_per_step": 1e3 * wall / steps, "value": n_atoms * steps / wall,
+                  "unit": "atom-steps/s"}
+
+
 def _timed(s, warmup, steps, dev):
     import torch
     s.step(warmup)
@@ -548,7 +579,8 @@ def sub_ensemble(args, ff, dev, steps, warmup):
     """The batched workload (64 boxes of 20..400 chains at 250..450 K, about 4.3M atoms), in the
     four forms that separate precision from batching: mixed batched and graph-replayed (one
     launch sequence for all boxes), FP64 batched, and one context per box in each precision.
-    Same warm-up and timed steps for each; the smallest box's forces against the oracle."""
+    Same warm-up and timed steps for each, from the relaxed melts; the smallest box's forces
+    against the oracle at the grown melts."""
     import numpy as np
     import oracle as O
     from paper_1001_3764_amd.md import MDSystem
@@ -559,6 +591,21 @@ def sub_ensemble(args, ff, dev, steps, warmup):
     pos, vel, types, boxes, chains = _concat(melts)
     N = pos.shape[1]
     log("ensemble64: %d boxes, %d atoms (%.1fs)" % (len(melts), N, time.perf_counter() - t))
+    # the smallest box's forces at the grown melts; then the grown melts relaxed (mixed, batched,
+    # graph-replayed) and every form timed from the relaxed state
+    s = MDSystem(ff, chains, boxes, list(wl.T0), pos, vel, types, chain_len=wl.chain_len, dt=wl.dt_fs,
+                 tau=wl.tau_fs, precision="mixed", cell_div=0, lj_kernel=0, use_graph=True, device=dev)
+    b = int(np.argmin([m.n_atoms for m in melts]))
+    off = sum(x.n_atoms for x in melts[:b])
+    m = melts[b]
+    f = s.forces()[:, off:off + m.n_atoms]
+    pos, vel, grown = relax_input(s, args.relax_steps, N, dev)
+    s.close()
+    O.set_threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
+    fo, _ = O.forces(ff, m.pos, m.types, m.box, m.chain_len)
+    frms = float(np.sqrt(np.mean(np.sum(fo ** 2, axis=0))))
+    smallest = {"box": b, "atoms": m.n_atoms,
+                "force_max_err_over_frms": float(np.max(np.sqrt(np.sum((f - fo) ** 2, axis=0))) / frms)}
     forms = {}
     R = kern = None
     for precision, graph in (("mixed", True), ("fp64", False)):
@@ -566,15 +613,6 @@ def sub_ensemble(args, ff, dev, steps, warmup):
                      tau=wl.tau_fs, precision=precision, cell_div=0, lj_kernel=0, use_graph=graph, device=dev)
         if precision == "mixed":
             R, kern = s.tuning()
-            b = int(np.argmin([m.n_atoms for m in melts]))
-            off = sum(x.n_atoms for x in melts[:b])
-            m = melts[b]
-            f = s.forces()[:, off:off + m.n_atoms]
-            O.set_threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
-            fo, _ = O.forces(ff, m.pos, m.types, m.box, m.chain_len)
-            frms = float(np.sqrt(np.mean(np.sum(fo ** 2, axis=0))))
-            smallest = {"box": b, "atoms": m.n_atoms,
-                        "force_max_err_over_frms": float(np.max(np.sqrt(np.sum((f - fo) ** 2, axis=0))) / frms)}
         tuning = list(s.tuning())
         wall = _timed(s, warmup, steps, dev)
         s.close()
@@ -606,6 +644,7 @@ def sub_ensemble(args, ff, dev, steps, warmup):
         log("ensemble64 %s: %.3e atom-steps/s" % (k, v["value"]))
     mb = forms["mixed_batched_graph"]["value"]
     return {"workload": wl.name, "boxes": len(melts), "atoms": N, "steps": steps, "warmup": warmup,
+            "relax_steps": args.relax_steps, "grown_melts_first_steps": grown,
             "value": mb, "unit": "atom-steps/s", "forms": forms,
             "mixed_batched_over_fp64_per_box": mb / forms["fp64_per_box"]["value"],
             "mixed_batched_over_fp64_batched": mb / forms["fp64_batched"]["value"],
@@ -615,8 +654,9 @@ def sub_ensemble(args, ff, dev, steps, warmup):
 
 def sub_melt30M(args, ff, dev, steps, warmup):
     """The largest single-box workload (30,000,000 atoms, 0.85 g/cm^3, 300 K): mixed
-    (graph-replayed) and plain FP64 rates over the same steps, the mixed form's sampled force
-    error against the oracle, and each phase's algorithmic HBM rate from HIP-event timings."""
+    (graph-replayed) and plain FP64 rates over the same steps from the relaxed melt, the mixed
+    form's sampled force error against the oracle at the grown melt, and each phase's algorithmic
+    HBM rate from HIP-event timings."""
     from paper_1001_3764_amd.md import MDSystem
     from pe_melt import WORKLOADS, build_melts
     wl = WORKLOADS["melt30M_mixed"]
@@ -624,13 +664,23 @@ def sub_melt30M(args, ff, dev, steps, warmup):
     melt = build_melts(wl, threads=16)[0]
     N = melt.n_atoms
     log("melt30M: %d atoms (%.1fs)" % (N, time.perf_counter() - t))
-    out = {"workload": wl.name, "atoms": N, "steps": steps, "warmup": warmup, "unit": "atom-steps/s",
-           "fits_in_driver_run": True}
-    s = MDSystem(ff, [melt.n_chains], melt.box[None, :], [wl.T0[0]], melt.pos, melt.vel, melt.types,
-                 chain_len=wl.chain_len, dt=wl.dt_fs, tau=wl.tau_fs, precision="mixed", cell_div=0, lj_kernel=0,
-                 use_graph=True, device=dev)
+    out = {"workload": wl.name, "atoms": N, "steps": steps, "warmup": warmup, "relax_steps": args.relax_steps,
+           "unit": "atom-steps/s", "fits_in_driver_run": True}
+
+    def system(precision, pos, vel, graph):
+        return MDSystem(ff, [melt.n_chains], melt.box[None, :], [wl.T0[0]], pos, vel, melt.types,
+                        chain_len=wl.chain_len, dt=wl.dt_fs, tau=wl.tau_fs, precision=precision, cell_div=0,
+                        lj_kernel=0, use_graph=graph, device=dev)
+
+    # forces at the grown melt, then the melt relaxed; the timed forms start from the relaxed state
+    s = system("mixed", melt.pos, melt.vel, True)
+    f_grown = s.forces()
+    pos, vel, out["grown_melt_first_steps"] = relax_input(s, args.relax_steps, N, dev)
+    s.close()
+    out["force_err_vs_fp64_oracle"] = sampled_force_error(ff, melt, f_grown, 2000, 30)
+    del f_grown
+    s = system("mixed", pos, vel, True)
     out["tuning"] = list(s.tuning())
-    out["force_err_vs_fp64_oracle"] = sampled_force_error(ff, melt, s.forces(), 2000, 30)
     wall = _timed(s, warmup, steps, dev)
     out["value"] = N * steps / wall
     out["ms_per_step"] = 1e3 * wall / steps
@@ -640,9 +690,7 @@ def sub_melt30M(args, ff, dev, steps, warmup):
     out["phases_ms_avg"] = {k: round(v, 4) for k, v in ph.items()}
     out["algorithmic_hbm_GBps_per_phase"] = {
         k: round(ALGO_BYTES_PER_ATOM[k] * N / (ph[k] * 1e-3) / 1e9, 1) for k in ALGO_BYTES_PER_ATOM}
-    s64 = MDSystem(ff, [melt.n_chains], melt.box[None, :], [wl.T0[0]], melt.pos, melt.vel, melt.types,
-                   chain_len=wl.chain_len, dt=wl.dt_fs, tau=wl.tau_fs, precision="fp64", cell_div=0, lj_kernel=0,
-                   use_graph=False, device=dev)
+    s64 = system("fp64", pos, vel, False)
     wall = _timed(s64, warmup, steps, dev)
     out["plain_fp64_gpu"] = {"value": N * steps / wall, "ms_per_step": 1e3 * wall / steps,
                              "tuning": list(s64.tuning()), "graph": False}
@@ -681,6 +729,9 @@ def run_other_workload(args):
 
     steps = args.steps if args.steps != 10000 else wl.steps   # the preset's own length by default
     s = make("mixed", list(wl.T0))
+    pos, vel, grown = relax_input(s, args.relax_steps, N, dev)
+    s.close()
+    s = make("mixed", list(wl.T0), pos, vel)
     R, kern = s.tuning()
     s.step(args.warmup)
     torch.cuda.synchronize(dev)
@@ -782,7 +833,7 @@ def run_other_workload(args):
     plain = None
     if not args.no_fp64:
         fp_steps = min(args.fp64_steps, 200)
-        s64 = make("fp64", list(wl.T0), graph=False)
+        s64 = make("fp64", list(wl.T0), pos, vel, graph=False)
         s64.step(10)
         torch.cuda.synchronize(dev)
         a = time.perf_counter()
@@ -802,7 +853,9 @@ def run_other_workload(args):
                    "chain_len": wl.chain_len, "density_g_cm3": wl.density, "tiles": wl.tiles,
                    "T0_K": [wl.T0[0], wl.T0[-1]], "thermostat": "berendsen", "tau_fs": wl.tau_fs,
                    "dt_fs": wl.dt_fs, "precision": "mixed (FP32 force, FP64 state)", "cell_div": R,
-                   "lj_kernel": kern, "graph": not args.no_graph, "bins_rebuilt_every_step": True},
+                   "lj_kernel": kern, "graph": not args.no_graph, "bins_rebuilt_every_step": True,
+                   "relax_steps": args.relax_steps},
+        "grown_melt_first_steps": grown,
         "ns_per_day": (1e3 / ms_per_step) * wl.dt_fs * 86400 * 1e-6,
         "plain_fp64_gpu": plain,
         "speedup_vs_plain_fp64": (value / plain["value"]) if plain else None,

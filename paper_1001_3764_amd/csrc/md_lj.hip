@@ -183,6 +183,47 @@ __device__ inline double uni(double x) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// The value of x on lane k (k wave-uniform), in scalar registers.
+__device__ inline int lane_value(int x, int k) { return __builtin_amdgcn_readlane(x, k); }
+__device__ inline double lane_value(double x, int k) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), k);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Minimum and maximum over lanes [0, K) (K = 1, 2, 4, 8 or 16; the other lanes of the first
+// 16-lane row hold the neutral element), as a vector-register value on every lane: a
+// butterfly over lane bits 0-3 within the row (xor 1, xor 2, the half-row mirror, xor 8), then
+// lane 0's result moved to every lane.
+template <typename T>
+__device__ inline T box_top();
+template <>
+__device__ inline int box_top<int>() { return 0x7fffffff; }
+template <>
+__device__ inline double box_top<double>() { return __builtin_huge_val(); }
+
+template <typename T>
+__device__ __forceinline__ T in_vgpr(T x) {
+  if constexpr (std::is_same<T, int>::value) asm volatile("" : "+v"(x));
+  return x;
+}
+
+template <int K, bool MAX, typename T>
+__device__ __forceinline__ T first_lanes_ext(T x) {
+  constexpr Xl lv[4] = {Xl::Quad1, Xl::Quad2, Xl::Mirror8, Xl::Ror8};
+#pragma unroll
+  for (int l = 0; (1 << l) < K; ++l) {
+    const T y = partner(x, lv[l]);
+    x = MAX ? max(x, y) : min(x, y);
+  }
+  return in_vgpr(lane_value(x, 0));
+}
+template <int K, typename T>
+__device__ __forceinline__ T first_lanes_min(T x) { return first_lanes_ext<K, false>(x); }
+template <int K, typename T>
+__device__ __forceinline__ T first_lanes_max(T x) { return first_lanes_ext<K, true>(x); }
+
 template <typename P>
 struct LjPair {
   P f12[4], f6[4], e12[4], e6[4], ecut[4];
@@ -492,7 +533,14 @@ struct Shift {
 template <typename Q>
 __device__ __forceinline__ void load_shifts(const Views& v, int b, Shift<Q>* shifts) {
   const Shift<Q>* __restrict__ tab = static_cast<const Shift<Q>*>(v.shift_tab) + (int64_t)b * kShiftSlots;
-  for (int c = (int)threadIdx.x; c < kShiftSlots; c += (int)blockDim.x) shifts[c] = tab[c];
+  static_assert(kShiftSlots == 128, "two entries per lane of one wave");
+  if (blockDim.x == 64) {   // one wave: two entries per lane, both loads in flight together
+    const Shift<Q> a = tab[threadIdx.x], c = tab[threadIdx.x + 64];
+    shifts[threadIdx.x] = a;
+    shifts[threadIdx.x + 64] = c;
+  } else {
+    for (int c = (int)threadIdx.x; c < kShiftSlots; c += (int)blockDim.x) shifts[c] = tab[c];
+  }
 }
 
 // Exclusive prefix sum of x >= 0 over the wave, bit plane by bit plane: the lanes below
@@ -517,26 +565,30 @@ __device__ __forceinline__ int fill_list(const Views& v, const BoxDev& B, int lc
   const int R = v.R, W = 2 * R + 1, W3 = W * W * W;
   const int M0 = B.M[0], M1 = B.M[1], M2 = B.M[2];
   const Cell3 k3 = cell_coords(lc, B);
-  int start[2], n[2];
+  // both cells' bounds are loaded together (a code past the stencil reads the home cell's
+  // and counts nothing)
+  int start[2], n[2], c[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    const int code = 2 * ln + h;
-    start[h] = 0;
-    n[h] = 0;
-    if (code < W3) {
-      const Cell3 o = stencil_offset(code, R);
-      int nx = k3.x + o.x, ny = k3.y + o.y, nz = k3.z + o.z;
-      nx += nx < 0 ? M0 : 0;
-      nx -= nx >= M0 ? M0 : 0;
-      ny += ny < 0 ? M1 : 0;
-      ny -= ny >= M1 ? M1 : 0;
-      nz += nz < 0 ? M2 : 0;
-      nz -= nz >= M2 ? M2 : 0;
-      const int c = B.cell_off + nx + M0 * (ny + M1 * nz);
-      start[h] = v.cell_start[c];
-      n[h] = v.cell_start[c + 1] - start[h];
-    }
+    const int code = min(2 * ln + h, W3 - 1);
+    const Cell3 o = stencil_offset(code, R);
+    int nx = k3.x + o.x, ny = k3.y + o.y, nz = k3.z + o.z;
+    nx += nx < 0 ? M0 : 0;
+    nx -= nx >= M0 ? M0 : 0;
+    ny += ny < 0 ? M1 : 0;
+    ny -= ny >= M1 ? M1 : 0;
+    nz += nz < 0 ? M2 : 0;
+    nz -= nz >= M2 ? M2 : 0;
+    c[h] = B.cell_off + nx + M0 * (ny + M1 * nz);
   }
+  int e[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    start[h] = v.cell_start[c[h]];
+    e[h] = v.cell_start[c[h] + 1];
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) n[h] = 2 * ln + h < W3 ? e[h] - start[h] : 0;
   int total;
   int f = wave_exclusive_scan(n[0] + n[1], total);
 #pragma unroll
@@ -819,77 +871,52 @@ void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
     const float fscale = UNI ? kInvFixF * cf.f6[0] : kInvFixF;
     for (int g0 = 0; g0 < hn; g0 += KMAX) {
       const int kc = min(KMAX, hn - g0);
-      Q hx[KMAX], hy[KMAX], hz[KMAX];
-      int32_t lo[KMAX], hti[KMAX];
-      uint32_t span[KMAX];
-      P ax[KMAX], ay[KMAX], az[KMAX];
-#pragma unroll
-      for (int k = 0; k < KMAX; ++k) {
-        ax[k] = ay[k] = az[k] = (P)0;
-        if (k < kc) {
-          const PayT q = pay[hs + g0 + k];
-          // FP64 homes go to scalar registers (measured faster); mixed ones stay in
-          // vector registers, where the scalar budget would otherwise spill
-          if constexpr (FP64) {
-            hx[k] = uni(q.x);
-            hy[k] = uni(q.y);
-            hz[k] = uni(q.z);
-          } else {
-            hx[k] = q.x;
-            hy[k] = q.y;
-            hz[k] = q.z;
-          }
-          const int32_t tag = FP64 ? uni(pay_tag(q)) : pay_tag(q);
-          const int32_t i = tag_index(tag);
-          const int32_t c0 = chain_first(i, ff);
-          lo[k] = max(i - ff.excl, c0);
-          span[k] = (uint32_t)(min(i + ff.excl, c0 + ff.chain_len - 1) - lo[k]);
-          hti[k] = tag_type(tag);
-        } else {
-          hx[k] = hy[k] = hz[k] = (Q)0;
-          lo[k] = 0;
-          span[k] = 0xffffffffu;   // excludes every candidate
-          hti[k] = 0;
-        }
+      // The group's homes, one per lane (lane k < kc holds home k), loaded together, with each
+      // home's exclusion window (the sorted indices within excl bonds along its chain); then
+      // broadcast to wave-uniform values.  A lane past the group holds zeros and a window
+      // that excludes every candidate.
+      PayT qh{};
+      int32_t lo_l = 0, ht_l = 0;
+      uint32_t span_l = 0xffffffffu;
+      if (ln < kc) {
+        qh = pay[hs + g0 + ln];
+        const int32_t i = tag_index(pay_tag(qh));
+        const int32_t c0 = chain_first(i, ff);
+        lo_l = max(i - ff.excl, c0);
+        span_l = (uint32_t)(min(i + ff.excl, c0 + ff.chain_len - 1) - lo_l);
+        ht_l = tag_type(pay_tag(qh));
       }
       // Cell path with a one-chunk list: keep only the candidates within the cutoff of the
       // box bounding the group's homes (about half of the stencil's atoms in a melt),
       // compacted in place.  Per axis |x - clamp(x, lo, hi)| <= |x - x_home| for every home
       // in the box, and each rounding is monotone, so the filter's r^2 (the pair test's
       // own operation order in the mixed form) never exceeds a pair's: no counted pair is
-      // dropped.  Each step's reads precede its writes and land at or above them.
+      // dropped.  Each batch's reads precede its writes and land at or above them.
       int ncand = total;    // list entries the step loop walks
       if (!LIST && total <= kListCap) {
         if (resident != 0) {
           load_list<LIST>(v, B, lc, 0, list[wave]);
           resident = 0;
         }
-        Q lox = hx[0], hix = hx[0], loy = hy[0], hiy = hy[0], loz = hz[0], hiz = hz[0];
-#pragma unroll
-        for (int k = 1; k < KMAX; ++k)
-          if (k < kc) {
-            lox = min(lox, hx[k]);
-            hix = max(hix, hx[k]);
-            loy = min(loy, hy[k]);
-            hiy = max(hiy, hy[k]);
-            loz = min(loz, hz[k]);
-            hiz = max(hiz, hz[k]);
-          }
+        // the box bounding the homes, reduced over the first KMAX lanes (in vector registers:
+        // the clamp reads both bounds of an axis)
+        const bool hv = ln < kc;
+        Q lox = first_lanes_min<KMAX>(hv ? qh.x : box_top<Q>()), hix = first_lanes_max<KMAX>(hv ? qh.x : -box_top<Q>());
+        Q loy = first_lanes_min<KMAX>(hv ? qh.y : box_top<Q>()), hiy = first_lanes_max<KMAX>(hv ? qh.y : -box_top<Q>());
+        Q loz = first_lanes_min<KMAX>(hv ? qh.z : box_top<Q>()), hiz = first_lanes_max<KMAX>(hv ? qh.z : -box_top<Q>());
         const double rc2_keep = ff.rc2 * (1.0 + 1e-12);
         int m = 0;
-        // kFilter steps per batch with their loads in flight together; every entry from total
-        // up to and including position tp is the sentinel (load_list pads the list), which
-        // never passes, so positions past the end clamp to tp; a batch reads all its entries
-        // before it writes any
         constexpr int kFilter = FP64 ? 2 : kFilterSteps;
-        const int tp = (total + 63) & ~63;
-        for (int t0 = 0; t0 < total; t0 += 64 * kFilter) {
-          uint32_t ent[kFilter];
-          Q jx[kFilter], jy[kFilter], jz[kFilter];
+        // NU steps from position t0 (all below the padded end, whose entries past total are the
+        // sentinel, which never passes); a batch reads all its entries before it writes any
+        auto batch = [&](int t0, auto nu) {
+          constexpr int NU = decltype(nu)::value;
+          uint32_t ent[NU];
+          Q jx[NU], jy[NU], jz[NU];
 #pragma unroll
-          for (int u = 0; u < kFilter; ++u) ent[u] = list[wave][min(t0 + 64 * u + ln, tp)];
+          for (int u = 0; u < NU; ++u) ent[u] = list[wave][t0 + 64 * u + ln];
 #pragma unroll
-          for (int u = 0; u < kFilter; ++u) {
+          for (int u = 0; u < NU; ++u) {
             const PayT q = pay[ent[u] >> 7];
             const Shift<Q> sh = shifts[ent[u] & 127];
             jx[u] = q.x + sh.x;
@@ -897,7 +924,7 @@ void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
             jz[u] = q.z + sh.z;
           }
 #pragma unroll
-          for (int u = 0; u < kFilter; ++u) {
+          for (int u = 0; u < NU; ++u) {
             const Q dx = jx[u] - clamp_box(jx[u], lox, hix), dy = jy[u] - clamp_box(jy[u], loy, hiy),
                     dz = jz[u] - clamp_box(jz[u], loz, hiz);
             bool pass;
@@ -909,10 +936,30 @@ void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
             if (pass) list[wave][m + lanes_below(bm)] = ent[u];
             m += __popcll(bm);
           }
-        }
+        };
+        // whole batches of kFilter steps with their loads in flight together, then single steps
+        const int tp = (total + 63) & ~63;
+        int t0 = 0;
+        for (; t0 + 64 * kFilter <= tp; t0 += 64 * kFilter) batch(t0, std::integral_constant<int, kFilter>());
+        for (; t0 < tp; t0 += 64) batch(t0, std::integral_constant<int, 1>());
         if (ln < ((m + 63) & ~63) - m) list[wave][m + ln] = kSentinelEntry;   // pad to whole steps
         ncand = m;
         resident = kCompacted;
+      }
+      // the homes broadcast to wave-uniform values (after the filter, which needs only their box)
+      Q hx[KMAX], hy[KMAX], hz[KMAX];
+      int32_t lo[KMAX], hti[KMAX];
+      uint32_t span[KMAX];
+      P ax[KMAX], ay[KMAX], az[KMAX];
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) {
+        ax[k] = ay[k] = az[k] = (P)0;
+        hx[k] = lane_value(qh.x, k);
+        hy[k] = lane_value(qh.y, k);
+        hz[k] = lane_value(qh.z, k);
+        lo[k] = lane_value(lo_l, k);
+        span[k] = (uint32_t)lane_value((int32_t)span_l, k);
+        hti[k] = lane_value(ht_l, k);
       }
       int nsteps = 0;       // candidate steps with a band pair or a close contact (wave-uniform)
       int32_t bmax = 0;     // bits of the largest r2s counted since the last band check
@@ -996,8 +1043,8 @@ void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
           sz *= fscale;
         }
         const int hk = ln >> (6 - LV);
+        const int32_t i = tag_index(__shfl(pay_tag(qh), hk));   // home hk's index, from lane hk
         if ((ln & ((64 >> LV) - 1)) == 0 && hk < kc) {
-          const int32_t i = tag_index(pay_tag(pay[hs + g0 + hk]));
           f[i] = sx;
           f[v.N + i] = sy;
           f[2 * v.N + i] = sz;
