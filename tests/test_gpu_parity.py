@@ -277,15 +277,21 @@ def test_graph_replay_is_bit_identical(ff, melt):
     b.close()
 
 
-def test_timed_step_matches_plain_step(ff, melt):
-    a = make_system(melt, ff, "mixed", 1)
-    b = make_system(melt, ff, "mixed", 1)
-    a.step(5)
-    ms = b.step_timed(5)
-    assert set(ms) >= {"lj", "bonded_kick", "integrate_bin"} and all(v >= 0 for v in ms.values())
-    pa, va = a.state()
-    pb, vb = b.state()
-    assert np.array_equal(pa, pb) and np.array_equal(va, vb)
+@pytest.mark.parametrize("precision,com,graph", [("mixed", False, False), ("mixed", True, True),
+                                                  ("fp64", False, True), ("fp64", True, False)])
+def test_timed_step_matches_plain_step(ff, melt, precision, com, graph):
+    """Plain steps (graph-replayed or not) and timed steps (an event around each phase) must give
+    the same bits, with and without the COM removal, at T0 > 0."""
+    a = make_system(melt, ff, precision, 1, T0=350.0, remove_com=com, use_graph=graph)
+    b = make_system(melt, ff, precision, 1, T0=350.0, remove_com=com, use_graph=False)
+    for n in (5, 3):
+        a.step(n)
+        ms = b.step_timed(n)
+        assert set(ms) >= {"lj", "bonded_kick", "integrate_bin"} and all(v >= 0 for v in ms.values())
+        pa, va = a.state()
+        pb, vb = b.state()
+        assert np.array_equal(pa, pb) and np.array_equal(va, vb)
+    assert a.energies()[0] == b.energies()[0]
     a.close()
     b.close()
 
