@@ -137,7 +137,7 @@ def cpu_baseline(ff, melt, budget_s=12.0, max_steps=20, threads=None):
             "cpu_model": cpu["model"], "host_logical_cpus": cpu["logical_cpus"]}
 
 
-def lj_roofline(N, box, rc, cand_stencil, pairs, lj_ms, kern, R):
+def lj_roofline(N, box, rc, cand_stencil, pairs, lj_ms, kern, R, homes):
     """Roofline position of the LJ kernel.  Algorithmic work per atom (the flop count of the
     paper's grid search): 8 flop for each of the C = 27 (L/M)^3 n candidates of the 27 cells of
     edge L/M >= rc (M = floor(L/rc)) and 13 flop for each pair inside the cutoff; one launch
@@ -150,10 +150,11 @@ def lj_roofline(N, box, rc, cand_stencil, pairs, lj_ms, kern, R):
     flop_stencil = LJ_FLOP_PER_CANDIDATE * cand_stencil + LJ_FLOP_PER_PAIR * pairs
     achieved = flop / (lj_ms * 1e-3) / 1e12
     kname = "k_lj_tile" if kern in (2, 3) else "k_lj_atom"
-    rec = counter_record("%s/R%d/K%d" % (kname, R, kern))
+    rec = counter_record("%s/R%d/K%d/H%d" % (kname, R, kern, homes))
     out = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
            "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": rec.get("bytes_per_launch"),
-           "kernel": "%s (Lennard-Jones, mixed, R=%d)" % (kname, R), "avg_launch_ms": round(lj_ms, 5),
+           "kernel": "%s (Lennard-Jones, mixed, R=%d, lj_kernel %d, %d atoms per wavefront)" % (kname, R, kern, homes),
+           "avg_launch_ms": round(lj_ms, 5),
            "flop_per_launch": flop, "candidates_per_atom_canonical": round(cand_canon / N, 2),
            "pairs_per_launch": pairs,
            "flop_basis": "per atom: 8 flop x 27 (L/M)^3 n candidates of the 27-cell grid of edge L/M >= rc "
@@ -182,6 +183,7 @@ def main():
                     help="steps of the mixed form that relax each grown melt before anything is timed")
     ap.add_argument("--cell-div", type=int, default=0, help="0 = autotune")
     ap.add_argument("--lj-kernel", type=int, default=0, help="0 = autotune")
+    ap.add_argument("--tile-homes", type=int, default=0, help="cell-tile atoms per wavefront (0 = autotune)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
@@ -231,7 +233,8 @@ def main():
     def mixed_system(pos, vel):
         return MDSystem(ff, [melt.n_chains], melt.box[None, :], [wl.T0[0]], pos, vel, melt.types,
                         chain_len=wl.chain_len, dt=wl.dt_fs, tau=wl.tau_fs, precision="mixed",
-                        cell_div=args.cell_div, lj_kernel=args.lj_kernel, use_graph=not args.no_graph, device=dev)
+                        cell_div=args.cell_div, lj_kernel=args.lj_kernel, use_graph=not args.no_graph, device=dev,
+                        tile_homes=args.tile_homes)
 
     # ---- the input: the grown melt (its forces checked against the oracle below), relaxed by
     # relax_steps steps of the mixed form toward T0; every timed form starts from that state ----
@@ -243,8 +246,8 @@ def main():
 
     # ---- mixed precision, graph-replayed: the headline ----
     s = mixed_system(p_start, v_start)
-    R, kern = s.tuning()
-    log("mixed: cell_div R=%d, lj kernel %d" % (R, kern))
+    R, kern, homes = s.tuning(homes=True)
+    log("mixed: cell_div R=%d, lj kernel %d, %d atoms per wavefront" % (R, kern, homes))
     M, _, _ = s.grid(0)
     s.step(args.warmup)
     torch.cuda.synchronize(dev)
@@ -395,7 +398,7 @@ def main():
 
     cand, pairs = candidate_and_pair_counts(pos_prof, melt.box, start_prof, M, R, ff["rc"], melt.n_chains,
                                             melt.chain_len)
-    roofline = lj_roofline(N, melt.box, ff["rc"], cand, pairs, phase_avg["lj"], kern, R)
+    roofline = lj_roofline(N, melt.box, ff["rc"], cand, pairs, phase_avg["lj"], kern, R, homes)
 
     # ---- force error of the mixed form against the FP64 oracle, at the grown melt and at the
     # state the timed run ended in (same positions on both sides) ----
@@ -484,7 +487,7 @@ def main():
                    "density_g_cm3": wl.density, "box_A": round(float(melt.box[0]), 4),
                    "T_init_K": wl.T_init[0], "T0_K": wl.T0[0], "thermostat": "berendsen",
                    "tau_fs": wl.tau_fs, "dt_fs": wl.dt_fs, "precision": "mixed (FP32 force, FP64 state)",
-                   "cell_div": R, "cells_per_dim": [int(x) for x in M], "lj_kernel": kern,
+                   "cell_div": R, "cells_per_dim": [int(x) for x in M], "lj_kernel": kern, "tile_homes": homes,
                    "graph": not args.no_graph, "bins_rebuilt_every_step": True,
                    "relax_steps": args.relax_steps},
         "grown_melt_first_steps": grown,
@@ -575,6 +578,19 @@ def sampled_force_error(ff, melt, f_gpu, n_sample, seed):
     return {"max_over_frms": float(d.max() / frms), "frms_estimate": frms, "atoms_sampled": int(n_sample)}
 
 
+def tuning_classes(sizes, tunings):
+    """The autotuner's choices over boxes of different sizes: for each distinct (cell_div,
+    lj_kernel, atoms per wavefront), how many boxes took it and the range of their atom counts."""
+    classes = {}
+    for n, t in zip(sizes, tunings):
+        key = "R%d/K%d/H%d" % tuple(t)
+        c = classes.setdefault(key, {"boxes": 0, "atoms_min": n, "atoms_max": n})
+        c["boxes"] += 1
+        c["atoms_min"] = min(c["atoms_min"], n)
+        c["atoms_max"] = max(c["atoms_max"], n)
+    return classes
+
+
 def sub_ensemble(args, ff, dev, steps, warmup):
     """The batched workload (64 boxes of 20..400 chains at 250..450 K, about 4.3M atoms), in the
     four forms that separate precision from batching: mixed batched and graph-replayed (one
@@ -618,6 +634,8 @@ def sub_ensemble(args, ff, dev, steps, warmup):
         s.close()
         forms["%s_batched%s" % (precision, "_graph" if graph else "")] = {
             "value": N * steps / wall, "ms_per_step": 1e3 * wall / steps, "tuning": tuning}
+    # one context per box, each autotuned for its own box (cell size, kernel, atoms per wavefront)
+    per_box_tuning = None
     for precision, graph in (("mixed", True), ("fp64", False)):
         ctxs = []
         off = 0
@@ -625,8 +643,10 @@ def sub_ensemble(args, ff, dev, steps, warmup):
             sl = slice(off, off + m.n_atoms)
             ctxs.append(MDSystem(ff, [m.n_chains], m.box[None, :], [wl.T0[b]], pos[:, sl], vel[:, sl], types[sl],
                                  chain_len=wl.chain_len, dt=wl.dt_fs, tau=wl.tau_fs, precision=precision,
-                                 cell_div=R, lj_kernel=kern, use_graph=graph, device=dev))
+                                 cell_div=0, lj_kernel=0, use_graph=graph, device=dev))
             off += m.n_atoms
+        if precision == "mixed":
+            per_box_tuning = tuning_classes([m.n_atoms for m in melts], [c.tuning(homes=True) for c in ctxs])
         for c in ctxs:
             c.step(warmup)
         import torch
@@ -649,6 +669,7 @@ def sub_ensemble(args, ff, dev, steps, warmup):
             "mixed_batched_over_fp64_per_box": mb / forms["fp64_per_box"]["value"],
             "mixed_batched_over_fp64_batched": mb / forms["fp64_batched"]["value"],
             "mixed_batched_over_mixed_per_box": mb / forms["mixed_per_box_graph"]["value"],
+            "per_box_tuning": per_box_tuning,
             "smallest_box_vs_oracle": smallest, "fits_in_driver_run": True}
 
 
@@ -811,7 +832,7 @@ def run_other_workload(args):
                 sl = slice(off, off + m.n_atoms)
                 ctxs.append(MDSystem(ff, [m.n_chains], m.box[None, :], [wl.T0[len(ctxs)]], pos[:, sl], vel[:, sl],
                                      types[sl], chain_len=wl.chain_len, dt=wl.dt_fs, tau=wl.tau_fs,
-                                     precision=precision, cell_div=R, lj_kernel=kern, use_graph=graph, device=dev))
+                                     precision=precision, cell_div=0, lj_kernel=0, use_graph=graph, device=dev))
                 off += m.n_atoms
             for c in ctxs:
                 c.step(5)
@@ -821,11 +842,14 @@ def run_other_workload(args):
                 c.step(box_steps)
             torch.cuda.synchronize(dev)
             b_ = time.perf_counter()
+            tunes = [c.tuning(homes=True) for c in ctxs]
             for c in ctxs:
                 c.close()
             per_box["%s_per_box%s" % (precision, "_graph" if graph else "")] = {
                 "value": N * box_steps / (b_ - a), "unit": "atom-steps/s", "steps": box_steps,
                 "ms_per_step_all_boxes": 1e3 * (b_ - a) / box_steps}
+            if precision == "mixed":
+                per_box["per_box_tuning"] = tuning_classes([m.n_atoms for m in melts], tunes)
             log("%s per box (%s): %.3e atom-steps/s" % (precision, "graph" if graph else "no graph",
                                                         N * box_steps / (b_ - a)))
         extra["per_box_forms"] = per_box
