@@ -2,8 +2,9 @@
 
 Default workload: 1,000 chains x 300 united atoms (300,000 atoms), 0.80 g/cm^3, Maxwell
 velocities at 500 K, Berendsen quench towards 300 K, dt = 1 fs, bins rebuilt every step,
-mixed precision (FP32 forces, FP64 state), hipGraph-replayed steps.  Beside it, in the same
-JSON line:
+mixed precision (FP32 forces, FP64 state), hipGraph-replayed steps.  The grown melt is first
+relaxed by --relax-steps steps of the same form (its forced close contacts resolve within a few
+tens of steps); every form is timed from the relaxed state.  Beside it, in the same JSON line:
   - the plain FP64 GPU form on the same input and steps (FP64 everywhere, no graph, its own
     autotuned grid and kernel), and the same FP64 form graph-replayed;
   - the force error of the mixed form against the FP64 oracle (at the grown melt and at the end
