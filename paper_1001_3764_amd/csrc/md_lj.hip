@@ -821,9 +821,9 @@ __device__ __forceinline__ void sum_homes(int ln, P (&ax)[KMAX], P (&ay)[KMAX], 
   sz = val[2];
 }
 
-// Occupancy targets (measured): the mixed form is held to 6 waves per SIMD (80 VGPRs; left
-// alone the compiler takes 82 and runs 5, and the few values it then spills sit outside the
-// pair loop: 8% faster); the FP64 form (K = 4) fits 8.
+// Occupancy targets (measured): the mixed form with 8 homes is held to 6 waves per SIMD (80
+// VGPRs; it uses 73, with no vector spills), 4 homes to 8 and 16 homes to 4; the FP64 form
+// (K = 4) fits 8.
 // LIST: neighbour-list mode with per-cell lists (the homes and the sorted order are those of
 // the last build, the payload the one refreshed since).
 template <bool FP64, bool ENERGY, bool UNI, int KMAX, bool BRANCHLESS, bool LIST = false>
