@@ -117,7 +117,7 @@ def canonical_candidates(n_atoms, box, rc):
     return 27.0 * float(np.prod(box / M)) * n_atoms / float(np.prod(box))
 
 
-def cpu_baseline(ff, melt, budget_s=12.0, max_steps=20, threads=None):
+def cpu_baseline(ff, melt, budget_s=12.0, max_steps=100, threads=None):
     import numpy as np
     import oracle as O
     threads = O.set_threads(threads or int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
