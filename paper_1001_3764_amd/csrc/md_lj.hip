@@ -979,9 +979,13 @@ void k_lj_tile(Views v, FFDev ff, LjPair<float> cf, LjPair<double> cd) {
           const int32_t jidx = tag_index(jt);
           const int jtype = tag_type(jt);
           bool near = false;    // a close contact on this lane in this step (mixed)
+          // the group's home count, re-read each step as an opaque scalar: the compiler then
+          // tests k < kc with a scalar compare per home instead of holding KMAX lane masks
+          int kcs = kc;
+          asm volatile("" : "+s"(kcs));
 #pragma unroll
           for (int k = 0; k < KMAX; ++k) {
-            if (k < kc) {
+            if (k < kcs) {
               const bool keep = (uint32_t)(jidx - lo[k]) > span[k];
               const int tt = UNI ? 0 : hti[k] * 2 + jtype;
               if constexpr (FP64)
