@@ -68,9 +68,10 @@ typedef enum {
 
 typedef enum {
   MD_PREC_FP64 = 0,   /* every force, energy and state update in double precision */
-  MD_PREC_MIXED = 1   /* pair and bonded forces in FP32 with FP32 per-atom accumulation;
-                         positions, velocities and the update in FP64; energy and virial
-                         sums in compensated FP64 */
+  MD_PREC_MIXED = 1   /* pair and bonded forces in FP32 with FP32 per-atom accumulation (pairs
+                         closer than 0.75 sigma, and pairs whose side of the cutoff FP32 cannot
+                         tell, are decided and evaluated in FP64); positions, velocities and the
+                         update in FP64; energy and virial sums in compensated FP64 */
 } md_precision;
 
 typedef enum {
