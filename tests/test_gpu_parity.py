@@ -251,6 +251,33 @@ def test_trajectory_100_steps(ff, melt, precision, xtol, kernel):
     s.close()
 
 
+@pytest.mark.parametrize("precision,kernel,homes", [("fp64", 2, 0), ("mixed", 1, 0), ("mixed", 2, 4),
+                                                    ("mixed", 2, 8), ("mixed", 2, 16)])
+def test_short_chains(ff, precision, kernel, homes):
+    """250 chains of 12 sites (3,000 atoms, a sixth of them CH3 ends): chain ends everywhere, so
+    the exclusion windows are clipped at most homes' chain ends and many bonded terms are end
+    terms.  Bins bit-exact, forces within the bar, and 40 Berendsen steps against the oracle."""
+    m = make_melt(250, chain_len=12, density=0.80, T=500.0, seed_melt=2024, seed_vel=2025, jitter=0.05)
+    s = make_system(m, ff, precision, 2, T0=350.0, lj_kernel=kernel, tile_homes=homes)
+    start, atoms = s.bins()
+    M, _, _ = s.grid(0)
+    _, ostart, oatoms = O.bin_atoms(O.cell_index(m.pos, m.box, M), int(np.prod(M)))
+    assert np.array_equal(start, ostart) and np.array_equal(atoms, oatoms)
+    fo, _ = O.forces(ff, m.pos, m.types, m.box, 12)
+    err = norm_err(s.forces(), fo)
+    print("short chains %s kernel %d homes %d: force error %.3e" % (precision, kernel, homes, err))
+    assert err <= (TOL_FP64 if precision == "fp64" else TOL_MIXED)
+    s.step(40)
+    p_o, v_o, f_o, e_o = O.run(ff, m.pos, m.vel, fo, m.types, m.box, 12, 40, T0=350.0)
+    p, v = s.state()
+    d = p - p_o
+    d -= m.box[:, None] * np.round(d / m.box[:, None])
+    assert np.abs(d).max() <= (1e-9 if precision == "fp64" else 1e-4)
+    e = s.energies()[0]
+    assert e["temperature"] == pytest.approx(e_o["temperature"], rel=1e-9 if precision == "fp64" else 1e-4)
+    s.close()
+
+
 def test_berendsen_quench_matches_oracle(ff, melt):
     s = make_system(melt, ff, "fp64", 1, T0=300.0)
     f0, _ = O.forces(ff, melt.pos, melt.types, melt.box, 300)
