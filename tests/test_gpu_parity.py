@@ -308,6 +308,40 @@ def test_orthorhombic_box(ff, melt, precision, kernel):
     s.close()
 
 
+@pytest.mark.parametrize("n_chains,R", [(56, 2), (90, 1)])
+@pytest.mark.parametrize("precision,kernel", [("fp64", 2), ("mixed", 1), ("mixed", 2), ("mixed", 6)])
+def test_smallest_boxes(ff, n_chains, R, precision, kernel):
+    """Boxes with the fewest cells the stencil allows, 2R + 1 per axis (5 at R = 2 in a 27.1 A box,
+    3 at R = 1 in a 31.7 A box; chains of 12 sites): every neighbour cell is reached through the
+    periodic wrap from some home.  Bins bit-exact, forces within the bar, 20 steps against the
+    oracle."""
+    from paper_1001_3764_amd.md import MDSystem
+    m = make_melt(n_chains, chain_len=12, density=0.80, T=500.0, seed_melt=77, seed_vel=78, jitter=0.05)
+    s = MDSystem(ff, [m.n_chains], m.box[None, :], [0.0], m.pos, m.vel, m.types, chain_len=12,
+                 precision=precision, cell_div=R, lj_kernel=kernel)
+    start, atoms = s.bins()
+    M, _, _ = s.grid(0)
+    assert [int(x) for x in M] == [2 * R + 1] * 3
+    _, ostart, oatoms = O.bin_atoms(O.cell_index(m.pos, m.box, M), int(np.prod(M)))
+    assert np.array_equal(start, ostart) and np.array_equal(atoms, oatoms)
+    # the oracle's grid search on the same stencil (a 27-cell grid of edge >= rc needs 3 rc), and
+    # its LJ part against the brute-force pair sum
+    fo, _ = O.forces(ff, m.pos, m.types, m.box, 12, R=R)
+    fb, _ = O.lj_brute(ff, m.pos, m.types, m.box, 12)
+    fl, _ = O.lj_cells(ff, m.pos, m.types, m.box, 12, R=R)
+    assert norm_err(fl, fb) <= 1e-12
+    err = norm_err(s.forces(), fo)
+    print("smallest box R=%d %s kernel %d: force error %.3e" % (R, precision, kernel, err))
+    assert err <= (TOL_FP64 if precision == "fp64" else TOL_MIXED)
+    s.step(20)
+    p_o, _, _, _ = O.run(ff, m.pos, m.vel, fo, m.types, m.box, 12, 20, R=R)
+    p, _ = s.state()
+    d = p - p_o
+    d -= m.box[:, None] * np.round(d / m.box[:, None])
+    assert np.abs(d).max() <= (1e-9 if precision == "fp64" else 1e-4)
+    s.close()
+
+
 def test_berendsen_quench_matches_oracle(ff, melt):
     s = make_system(melt, ff, "fp64", 1, T0=300.0)
     f0, _ = O.forces(ff, melt.pos, melt.types, melt.box, 300)
