@@ -342,6 +342,35 @@ def test_smallest_boxes(ff, n_chains, R, precision, kernel):
     s.close()
 
 
+@pytest.mark.parametrize("precision,kernel", [("fp64", 2), ("mixed", 1), ("mixed", 2), ("mixed", 6)])
+def test_sparse_box(ff, precision, kernel):
+    """Six 300-site chains at 0.05 g/cm^3 (1,800 atoms in a 94 A box): most cells empty, most
+    stencils nearly so, so the empty-cell, empty-group and short-list paths all run.  Bins
+    bit-exact, forces within the bar, 30 steps against the oracle."""
+    from paper_1001_3764_amd.md import MDSystem
+    m = make_melt(6, chain_len=300, density=0.05, T=500.0, seed_melt=91, seed_vel=92, jitter=0.05)
+    s = MDSystem(ff, [m.n_chains], m.box[None, :], [0.0], m.pos, m.vel, m.types, chain_len=300,
+                 precision=precision, cell_div=2, lj_kernel=kernel)
+    start, atoms = s.bins()
+    M, _, _ = s.grid(0)
+    counts = np.diff(start)
+    assert (counts == 0).mean() > 0.5
+    _, ostart, oatoms = O.bin_atoms(O.cell_index(m.pos, m.box, M), int(np.prod(M)))
+    assert np.array_equal(start, ostart) and np.array_equal(atoms, oatoms)
+    fo, _ = O.forces(ff, m.pos, m.types, m.box, 300)
+    err = norm_err(s.forces(), fo)
+    print("sparse box %s kernel %d: %.0f%% empty cells, force error %.3e"
+          % (precision, kernel, 100 * (counts == 0).mean(), err))
+    assert err <= (TOL_FP64 if precision == "fp64" else TOL_MIXED)
+    s.step(30)
+    p_o, _, _, _ = O.run(ff, m.pos, m.vel, fo, m.types, m.box, 300, 30)
+    p, _ = s.state()
+    d = p - p_o
+    d -= m.box[:, None] * np.round(d / m.box[:, None])
+    assert np.abs(d).max() <= (1e-9 if precision == "fp64" else 1e-4)
+    s.close()
+
+
 def test_berendsen_quench_matches_oracle(ff, melt):
     s = make_system(melt, ff, "fp64", 1, T0=300.0)
     f0, _ = O.forces(ff, melt.pos, melt.types, melt.box, 300)
