@@ -371,6 +371,31 @@ def test_sparse_box(ff, precision, kernel):
     s.close()
 
 
+@pytest.mark.parametrize("R", [1, 2])
+@pytest.mark.parametrize("precision,kernel", [("fp64", 2), ("mixed", 1), ("mixed", 2), ("mixed", 6)])
+def test_compressed_melt(ff, melt, R, precision, kernel):
+    """The 3,000-atom melt squeezed to 0.8 of its box edge (1.95 times the density): stencils
+    longer than one list chunk at R = 2 (walked unfiltered, chunk by chunk), and thousands of
+    pairs closer than 0.75 sigma, so groups exceed the close-contact queue and take the full
+    walk.  Forces within the bar, and 5 steps against the oracle."""
+    from paper_1001_3764_amd.md import MDSystem
+    box = melt.box * 0.8
+    pos = np.ascontiguousarray(melt.pos * 0.8)
+    s = MDSystem(ff, [melt.n_chains], box[None, :], [0.0], pos, melt.vel, melt.types, chain_len=300,
+                 precision=precision, cell_div=R, lj_kernel=kernel)
+    fo, _ = O.forces(ff, pos, melt.types, box, 300)
+    err = norm_err(s.forces(), fo)
+    print("compressed R=%d %s kernel %d: force error %.3e" % (R, precision, kernel, err))
+    assert err <= (TOL_FP64 if precision == "fp64" else TOL_MIXED)
+    s.step(5)
+    p_o, _, _, _ = O.run(ff, pos, melt.vel, fo, melt.types, box, 300, 5)
+    p, _ = s.state()
+    d = p - p_o
+    d -= box[:, None] * np.round(d / box[:, None])
+    assert np.abs(d).max() <= (1e-9 if precision == "fp64" else 1e-4)
+    s.close()
+
+
 def test_berendsen_quench_matches_oracle(ff, melt):
     s = make_system(melt, ff, "fp64", 1, T0=300.0)
     f0, _ = O.forces(ff, melt.pos, melt.types, melt.box, 300)
