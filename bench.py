@@ -671,7 +671,7 @@ def sub_ensemble(args, ff, dev, steps, warmup):
             "mixed_batched_over_fp64_batched": mb / forms["fp64_batched"]["value"],
             "mixed_batched_over_mixed_per_box": mb / forms["mixed_per_box_graph"]["value"],
             "per_box_tuning": per_box_tuning,
-            "smallest_box_vs_oracle": smallest, "fits_in_driver_run": True}
+            "smallest_box_vs_oracle": smallest, "fits_in_default_run": True}
 
 
 def sub_melt30M(args, ff, dev, steps, warmup):
@@ -687,7 +687,7 @@ def sub_melt30M(args, ff, dev, steps, warmup):
     N = melt.n_atoms
     log("melt30M: %d atoms (%.1fs)" % (N, time.perf_counter() - t))
     out = {"workload": wl.name, "atoms": N, "steps": steps, "warmup": warmup, "relax_steps": args.relax_steps,
-           "unit": "atom-steps/s", "fits_in_driver_run": True}
+           "unit": "atom-steps/s", "fits_in_default_run": True}
 
     def system(precision, pos, vel, graph):
         return MDSystem(ff, [melt.n_chains], melt.box[None, :], [wl.T0[0]], pos, vel, melt.types,
